@@ -1,0 +1,34 @@
+"""Plain FP64 CPU oracle for the dual-smoothing method (P-APG) on least-squares convex regression.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or execute anything in
+this package: only the tests, the smoke check of the package entry file and the CPU-baseline leg
+of the benchmark use it.  It shares no code with the HIP library (no kernels, headers, helpers,
+constants or pre/post-processing); both consume the same seeded inputs from the workload
+generators, which contain none of the method's arithmetic.
+
+Contents
+--------
+``papg``   the method itself: the matrix-free constraint operator C and its adjoint, the closed-form
+           Step 1 for the singleton partition (K = N), the Lipschitz constant by power iteration,
+           the P-APG loop, the stopping report and the feasible-repair certificate.
+``exact``  an independent exact solver for tiny N that builds A1 and A2 explicitly from the
+           T_l blocks of Definition ``def:A1A2`` and solves the dual as a non-negative least
+           squares problem (Lawson-Hanson, via scipy).
+
+All arithmetic is float64 with numpy's default round-to-nearest.  Each function cites the
+passage of the paper (Aybat & Wang, "A Parallelizable Dual Smoothing Method for Large Scale
+Convex Regression Problems", arXiv:1608.02227) that it follows.
+"""
+from .papg import (  # noqa: F401
+    pair_residual,
+    pair_adjoint,
+    primal_from_dual,
+    dual_objective,
+    primal_objective,
+    lipschitz,
+    fista_schedule,
+    papg,
+    kkt_report,
+    repair_certificate,
+)
+from .exact import explicit_constraints, exact_solve  # noqa: F401

@@ -1,0 +1,283 @@
+"""P-APG for the Tikhonov-regularized convex-regression QP, singleton partition, plain FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): not part of the product path.
+
+Problem (Section 2.1, eq. ``regularize``):
+    minimize  r_g(y, xi) = 1/2 ||y - ybar||^2 + g/2 ||xi||^2
+    over      y in R^N, xi = [xi_l] in R^{N n}
+    s.t.      A1 y + A2 xi >= 0,
+one row per ordered pair (i, j), i != j, in lexicographic order (Section 2, Definition
+``def:A1A2``): the row of pair (i, j) reads  y_j - y_i + xi_i^T (x_i - x_j) >= 0  (eq. ``original``).
+``g`` (gamma) is the Tikhonov weight.
+
+Partition: every point is its own block (K = N), so every pair constraint is dualized and the
+local set Q of Definition ``def:C`` is the whole space.  The dual multipliers theta are held as
+an N x N array ``lam`` whose entry (i, j) belongs to the row of pair (i, j); the diagonal is
+not a pair and is kept at zero.
+
+Parity pins for every function here live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------------------------
+# The constraint operator C = [A1 A2] and its adjoint (Definition def:A1A2; matrix-free products
+# as described in Section 2.5).
+# ---------------------------------------------------------------------------------------------
+
+def pair_residual(x: np.ndarray, y: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """Constraint values C eta for eta = (y, xi): s_ij = y_j - y_i + xi_i^T (x_i - x_j).
+
+    Follows Definition ``def:A1A2``: row r of T_i picks y_j - y_i, and X_i = -T_i X picks
+    (x_i - x_j)^T xi_i.  The product xi_i^T (x_i - x_j) is expanded as xi_i^T x_i - xi_i^T x_j
+    so that the N^2 n work is one matrix product.  Returns an N x N array with a zero diagonal.
+    """
+    d = np.einsum("ik,ik->i", xi, x)            # xi_i^T x_i
+    s = y[None, :] - y[:, None] + d[:, None] - xi @ x.T
+    np.fill_diagonal(s, 0.0)
+    return s
+
+
+def pair_adjoint(x: np.ndarray, lam: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """C^T lam = (A1^T lam, A2^T lam) for multipliers lam (N x N, entry (i, j) = pair (i, j)).
+
+    (A1^T lam)_m collects +lam_im from the rows where m is the second index and -lam_mj from the
+    rows where m is the first index: column sum minus row sum.
+    (A2^T lam)_m = sum_j lam_mj (x_m - x_j) = (row sum)_m x_m - (Lam X)_m, because only the rows
+    (m, j) touch xi_m (A2 is block diagonal).
+    """
+    lam = np.array(lam, dtype=np.float64, copy=True)
+    np.fill_diagonal(lam, 0.0)
+    row = lam.sum(axis=1)
+    col = lam.sum(axis=0)
+    u = col - row
+    w = row[:, None] * x - lam @ x
+    return u, w
+
+
+def primal_from_dual(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray
+                     ) -> tuple[np.ndarray, np.ndarray]:
+    """Step 1 of P-APG (Fig. ``fig:papg``) with Q the whole space.
+
+    The minimizer of 1/2||y - ybar||^2 + g/2||xi||^2 - <C^T lam, eta> is the stationary point
+    y - ybar = A1^T lam, g xi = A2^T lam.  This is also eta(theta) of eq. ``dual gradient``.
+    """
+    u, w = pair_adjoint(x, lam)
+    return ybar + u, w / gamma
+
+
+def primal_objective(ybar: np.ndarray, gamma: float, y: np.ndarray, xi: np.ndarray) -> float:
+    """r_gamma(y, xi) of eq. ``regularize``."""
+    return 0.5 * float(np.sum((y - ybar) ** 2)) + 0.5 * gamma * float(np.sum(xi ** 2))
+
+
+def dual_objective(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray) -> float:
+    """g_gamma(lam) of eq. ``eq:g_gamma``: the Lagrangian at its unique minimizer eta(lam)."""
+    y, xi = primal_from_dual(x, ybar, gamma, lam)
+    s = pair_residual(x, y, xi)
+    lam0 = np.array(lam, dtype=np.float64, copy=True)
+    np.fill_diagonal(lam0, 0.0)
+    return primal_objective(ybar, gamma, y, xi) - float(np.sum(lam0 * s))
+
+
+# ---------------------------------------------------------------------------------------------
+# Lipschitz constant of the dual gradient (eq. eq:lischitz): L = sigma_max(C)^2 / gamma.
+# ---------------------------------------------------------------------------------------------
+
+def lipschitz(x: np.ndarray, gamma: float, rtol: float = 1e-8, max_iter: int = 300
+              ) -> tuple[float, float, int]:
+    """Estimate sigma_max(C)^2 by power iteration on C^T C and return (L, sigma2, iterations).
+
+    The paper computes sigma_max in a "Preprocess" step (Section 4) without naming a routine.
+    Reading used here: start from v_y,l = -1 + 2 l / (N - 1) (l = 0..N-1, a ramp: a constant
+    v_y lies in the kernel of A1) and v_xi = 1, normalized over (y, xi); each iteration forms
+    z = C v, takes the Rayleigh quotient ||C v||^2 as the estimate, then v <- C^T z / ||C^T z||;
+    stop when two successive estimates agree to ``rtol`` (relative) or after ``max_iter``.
+    """
+    N, n = x.shape
+    vy = -1.0 + 2.0 * np.arange(N) / max(N - 1, 1)
+    vxi = np.ones((N, n))
+    nrm = math.sqrt(float(np.sum(vy ** 2) + np.sum(vxi ** 2)))
+    vy /= nrm
+    vxi /= nrm
+    est = 0.0
+    it = 0
+    for it in range(1, max_iter + 1):
+        z = pair_residual(x, vy, vxi)
+        new = float(np.sum(z ** 2))
+        gy, gxi = pair_adjoint(x, z)
+        nrm = math.sqrt(float(np.sum(gy ** 2) + np.sum(gxi ** 2)))
+        if nrm == 0.0:
+            est = new
+            break
+        vy, vxi = gy / nrm, gxi / nrm
+        done = abs(new - est) <= rtol * new
+        est = new
+        if done:
+            break
+    return est / gamma, est, it
+
+
+# ---------------------------------------------------------------------------------------------
+# The P-APG loop (Fig. fig:papg; APG of Fig. fig:apg applied to the dual eq:dual-problem).
+# ---------------------------------------------------------------------------------------------
+
+def fista_schedule(iters: int) -> tuple[np.ndarray, np.ndarray]:
+    """t_k for k = 1..iters+1 and beta_k = (t_k - 1) / t_{k+1} for k = 1..iters (Steps 3-4).
+
+    ``t[k]`` and ``beta[k]`` are 1-based (index 0 unused)."""
+    t = np.zeros(iters + 2)
+    beta = np.zeros(iters + 1)
+    t[1] = 1.0
+    for k in range(1, iters + 1):
+        t[k + 1] = (1.0 + math.sqrt(1.0 + 4.0 * t[k] * t[k])) / 2.0
+        beta[k] = (t[k] - 1.0) / t[k + 1]
+    return t, beta
+
+
+def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | None = None,
+         max_iters: int = 100000, check_every: int = 50, lam0: np.ndarray | None = None,
+         momentum: bool = True, trace: list | None = None, iterates: list | None = None) -> dict:
+    """Run P-APG (Fig. ``fig:papg``) from theta^0 = lam0 (default 0, as in Theorem ``bound``).
+
+    Iteration k >= 1, with lam_tilde^1 = lam^0 and t_1 = 1:
+      1. eta^k = argmin_eta {1/2||y - ybar||^2 + g/2||xi||^2 - <C^T lam_tilde^k, eta>}
+      2. lam^k = (lam_tilde^k - C eta^k / L)_+
+      3. t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+      4. lam_tilde^{k+1} = lam^k + (t_k - 1)/t_{k+1} (lam^k - lam^{k-1})
+    ``momentum=False`` sets the extrapolation weight to zero, which is plain projected dual
+    gradient ascent (eq. ``eq:gd-rate``).  Every ``check_every`` iterations the stopping report
+    of ``kkt_report`` is evaluated at (lam^k, eta(lam^k)); the loop stops once its ``kkt`` is at
+    most ``tol``.  ``iterates``, when given, receives (k, lam^k) for every k.
+    """
+    N = x.shape[0]
+    if L is None:
+        L = lipschitz(x, gamma)[0]
+    lam_prev = np.zeros((N, N)) if lam0 is None else np.array(lam0, dtype=np.float64, copy=True)
+    np.fill_diagonal(lam_prev, 0.0)
+    lam_tilde = lam_prev.copy()
+    t = 1.0
+    rep = None
+    k = 0
+    status = "max_iters"
+    for k in range(1, max_iters + 1):
+        y, xi = primal_from_dual(x, ybar, gamma, lam_tilde)                    # step 1
+        s = pair_residual(x, y, xi)
+        lam = np.maximum(0.0, lam_tilde - s / L)                               # step 2
+        np.fill_diagonal(lam, 0.0)
+        t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0                    # step 3
+        beta = (t - 1.0) / t_next if momentum else 0.0
+        lam_tilde = lam + beta * (lam - lam_prev)                              # step 4
+        lam_prev = lam
+        t = t_next
+        if iterates is not None:
+            iterates.append((k, lam.copy()))
+        if k % check_every == 0 or k == max_iters:
+            rep = kkt_report(x, ybar, gamma, lam)
+            if trace is not None:
+                trace.append((k, rep))
+            if rep["kkt"] <= tol:
+                status = "converged"
+                break
+    y, xi = primal_from_dual(x, ybar, gamma, lam_prev)
+    if rep is None or rep.get("k") != k:
+        rep = kkt_report(x, ybar, gamma, lam_prev)
+    rep["k"] = k
+    return {"y": y, "xi": xi, "lam": lam_prev, "L": L, "iters": k, "status": status,
+            "report": rep}
+
+
+# ---------------------------------------------------------------------------------------------
+# Stopping test and reported metrics.
+# ---------------------------------------------------------------------------------------------
+
+def kkt_report(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray,
+               y: np.ndarray | None = None, xi: np.ndarray | None = None) -> dict:
+    """Optimality measures of a dual point lam >= 0 and its primal eta(lam).
+
+    The paper does not define a KKT residual.  Reading used here: the KKT conditions of the
+    regularized QP are stationarity (y - ybar = A1^T lam, g xi = A2^T lam: Step 1), dual
+    feasibility (lam >= 0: the projection of Step 2), primal feasibility s = C eta >= 0 and
+    complementarity lam_ij s_ij = 0.  The last two are measured by the natural residual of the
+    bound-constrained dual, |min(lam_ij, s_ij)| over all pairs, and the stationarity of a given
+    (y, xi) by its max-norm distance from the closed form.  All are divided by
+    S_y = max(1, max ybar - min ybar):
+
+        kkt = max(max_ij |min(lam_ij, s_ij)|, ||y - ybar - A1^T lam||_inf,
+                  ||g xi - A2^T lam||_inf / g) / S_y
+
+    Also returned: the paper's normalized infeasibility ||(C eta)_-||_2 / sqrt(N^2 - N) and
+    normalized duality gap |lam^T C eta| / (N^2 - N) (both defined in Section 4.1), the largest
+    violation, g(lam), r_g(eta) and sum lam_ij s_ij.
+    """
+    N = x.shape[0]
+    lam = np.array(lam, dtype=np.float64, copy=True)
+    np.fill_diagonal(lam, 0.0)
+    u, w = pair_adjoint(x, lam)
+    y_cf, xi_cf = ybar + u, w / gamma
+    if y is None:
+        y = y_cf
+    if xi is None:
+        xi = xi_cf
+    s = pair_residual(x, y, xi)
+    off = ~np.eye(N, dtype=bool)
+    sy = max(1.0, float(ybar.max() - ybar.min()))
+    nat = float(np.max(np.abs(np.minimum(lam, s)[off]))) if N > 1 else 0.0
+    stat_y = float(np.max(np.abs(y - y_cf)))
+    stat_xi = float(np.max(np.abs(gamma * xi - w))) / gamma
+    neg = np.minimum(s[off], 0.0)
+    pairs = N * N - N
+    comp = float(np.sum(lam * s))
+    r = primal_objective(ybar, gamma, y, xi)
+    return {
+        "kkt": max(nat, stat_y, stat_xi) / sy,
+        "nat_res_max": nat / sy,
+        "stat_y": stat_y / sy,
+        "stat_xi": stat_xi / sy,
+        "max_viol": float(max(0.0, -s[off].min())) / sy if N > 1 else 0.0,
+        "infeas_rms": float(math.sqrt(np.sum(neg ** 2) / pairs)) if N > 1 else 0.0,
+        "dual_gap_paper": abs(comp) / pairs if N > 1 else 0.0,
+        "comp_sum": comp,
+        "primal_obj": r,
+        "dual_obj": r - comp,
+        "scale": sy,
+    }
+
+
+def repair_certificate(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray) -> dict:
+    """A feasible primal point built from eta(lam) and the certified gap it gives.
+
+    The fitted function f(z) = max_i (y_i + xi_i^T (z - x_i)) is convex; y'_j = f(x_j) and
+    xi'_j = xi_{i*(j)} with i*(j) the maximizing piece (j itself unless some other piece is
+    strictly larger; lowest index among ties) satisfy every pair constraint, so
+    p*_g <= r_g(y', xi') and, by weak duality, G = r_g(y', xi') - g(lam) >= p*_g - g(lam) >= 0.
+    Theorem ``thm:rate`` then bounds ||y(lam) - y*_g||^2 + g ||xi(lam) - xi*_g||^2 <= 2 G.
+    The largest |f(x_j) - y_j| equals the largest constraint violation of eta(lam).
+    """
+    N = x.shape[0]
+    y, xi = primal_from_dual(x, ybar, gamma, lam)
+    s = pair_residual(x, y, xi)                  # s_jj = 0 stands for piece j itself
+    # f(x_j) = max_i (y_i + xi_i^T (x_j - x_i)) = y_j - min_i s_ij
+    colmin = s.min(axis=0)
+    y_rep = y - colmin
+    istar = np.arange(N)
+    viol = colmin < 0.0
+    istar[viol] = np.argmin(s[:, viol], axis=0)
+    xi_rep = xi[istar]
+    g = dual_objective(x, ybar, gamma, lam)
+    r_rep = primal_objective(ybar, gamma, y_rep, xi_rep)
+    G = r_rep - g
+    return {
+        "y_rep": y_rep,
+        "xi_rep": xi_rep,
+        "piece": istar,
+        "primal_rep": r_rep,
+        "dual_obj": g,
+        "cert_gap": G,
+        "y_err_bound": math.sqrt(max(0.0, 2.0 * G)),
+        "max_fit_change": float(np.max(np.abs(y_rep - y))),
+    }
