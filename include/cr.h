@@ -1,0 +1,210 @@
+/*
+ * cr.h - C ABI of libcr: dual-smoothing (P-APG) least-squares convex regression on one
+ * MI355X (gfx950) GPU.
+ *
+ * Problem (Aybat & Wang, arXiv:1608.02227, Section 2.1, eq. "regularize"): given locations
+ * x_1..x_N in R^n and observations ybar_1..ybar_N, find fitted values y in R^N and
+ * subgradients xi_1..xi_N in R^n minimizing
+ *     1/2 sum_l (y_l - ybar_l)^2 + delta/2 sum_l ||xi_l||^2
+ * subject to the N(N-1) pair constraints  y_j - y_i + xi_i^T (x_i - x_j) >= 0,  i != j
+ * (eq. "original"; Definition "def:A1A2" orders the pairs lexicographically).  delta is the
+ * Tikhonov weight the paper calls gamma.
+ *
+ * Method: P-APG (Fig. "fig:papg") with every pair constraint dualized (each point its own
+ * block).  Step 1 is then closed-form: y = ybar + A1^T lam~, xi = A2^T lam~ / delta; Step 2 is
+ * the projected dual step lam = (lam~ - C eta / L)_+; Steps 3-4 are the FISTA momentum.  The
+ * Lipschitz constant is L = sigma_max(C)^2 / delta (eq. "eq:lischitz"), estimated by power
+ * iteration unless the caller supplies it.  The multipliers lam are an N x N matrix whose
+ * entry (i, j) belongs to the constraint of pair (i, j); the diagonal is always 0.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are row-major and dense: x is N x n, xi is N x n, lam is N x N.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory on the
+ *     options' device.  The library copies what it needs; it keeps no caller pointer after a
+ *     call returns (serving entry points copy inputs at submission).
+ *   - Return value: CR_OK (0) or a negative CR_E* code; cr_strerror() names it.  Outputs are
+ *     left untouched on CR_EINVAL / CR_ENOMEM / CR_EDEVICE.  On CR_ENOCONV and CR_ENUMERIC the
+ *     outputs and the report describe the last iterate.
+ *   - Thread safety: separate solvers and contexts may be used from separate threads; one
+ *     solver or context must not be used by two threads at once.
+ */
+#ifndef CR_H
+#define CR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CR_OK 0
+#define CR_EINVAL (-1)   /* bad argument: N < 1, n < 1, delta <= 0, tol <= 0, non-finite data */
+#define CR_ENOMEM (-2)   /* device memory (or a context's byte budget) cannot hold the state */
+#define CR_ENOCONV (-3)  /* iteration or time budget exhausted before the tolerance */
+#define CR_ENUMERIC (-4) /* NaN or Inf met in the iterates */
+#define CR_EDEVICE (-5)  /* a HIP call failed, or no gfx950 device */
+#define CR_EAGAIN (-6)   /* serving: the request has not finished yet */
+#define CR_ENOTFOUND (-7)/* serving: unknown request id */
+
+/* Arithmetic of the multiplier state and of the pair pass. */
+typedef enum {
+    CR_FP64 = 0,        /* lam stored in FP64, FP64 pair pass (FP64 MFMA contractions)          */
+    CR_MIXED_FP32 = 1,  /* lam stored in FP32 with FP32 MFMA contractions until progress stalls,  */
+                        /* then FP64 refinement from the promoted multipliers                     */
+    CR_MIXED_BF16 = 2   /* as CR_MIXED_FP32 but the low-precision phase stores lam in BF16       */
+} cr_precision;
+
+typedef struct {
+    int32_t precision;       /* cr_precision; default CR_FP64 */
+    int32_t check_every;     /* stopping test every m iterations; default 50 */
+    int64_t max_iters;       /* iteration budget; default 2,000,000 */
+    double time_budget_s;    /* wall-clock budget of the iteration loop; 0 = none */
+    double L;                /* > 0: use this Lipschitz constant; 0: power iteration (default) */
+    int32_t power_max_iters; /* power-iteration cap; default 300 */
+    double power_rtol;       /* power-iteration relative stopping change; default 1e-8 */
+    int32_t momentum;        /* 1: P-APG (default); 0: plain projected dual gradient ascent */
+    int32_t certificate;     /* 1: compute the feasible repair and certified gap (default 1) */
+    int32_t device;          /* HIP device ordinal; default 0 */
+    void *stream;            /* hipStream_t to run on; NULL: the library's own stream */
+    int32_t stall_checks;    /* mixed modes: switch to FP64 after this many checks without a
+                                10% improvement of the KKT residual; default 4 */
+    int32_t reserved[7];
+} cr_options;
+
+typedef struct {
+    int32_t status;          /* CR_OK, CR_ENOCONV or CR_ENUMERIC */
+    int32_t precision;       /* precision mode used */
+    int64_t iters;           /* P-APG iterations taken */
+    int64_t iters_low;       /* of which in the low-precision phase (mixed modes) */
+    double seconds;          /* wall time of the whole fit, preprocessing included */
+    double preprocess_seconds; /* wall time of the Lipschitz estimate */
+    double L;                /* Lipschitz constant used */
+    double sigma2;           /* sigma_max(C)^2 estimate (0 when L was given) */
+    int32_t power_iters;     /* power iterations taken */
+    int32_t checks;          /* stopping tests evaluated */
+    /* Stopping quantities at the returned multipliers, all divided by
+       S_y = max(1, max ybar - min ybar):
+         kkt = max(max_ij |min(lam_ij, s_ij)|, stat_y, stat_xi) with s = C eta(lam). */
+    double kkt;
+    double nat_res_max;      /* max_ij |min(lam_ij, s_ij)| / S_y                           */
+    double stat_y;           /* ||y - ybar - A1^T lam||_inf / S_y of the returned y            */
+    double stat_xi;          /* ||delta xi - A2^T lam||_inf / (delta S_y) of the returned xi   */
+    double max_viol;         /* max_ij (-s_ij)_+ / S_y                                       */
+    double infeas_rms;       /* ||(C eta)_-||_2 / sqrt(N^2 - N)      (paper, Section 4.1)     */
+    double dual_gap_paper;   /* |lam^T C eta| / (N^2 - N)            (paper, Section 4.1)     */
+    double comp_sum;         /* sum_ij lam_ij s_ij                                           */
+    double primal_obj;       /* r_delta(eta(lam))                                            */
+    double dual_obj;         /* g_delta(lam) = primal_obj - comp_sum                          */
+    double scale;            /* S_y */
+    /* Certificate (options.certificate): the max-affine repair of eta(lam) is feasible, so
+       cert_gap = r_delta(repair) - g_delta(lam) >= p* - g_delta(lam) >= 0 and, by the paper's
+       Theorem "thm:rate", ||y(lam) - y*||_2 <= y_err_bound = sqrt(2 cert_gap). */
+    double cert_primal;
+    double cert_gap;
+    double y_err_bound;
+    double reserved[6];
+} cr_report;
+
+/* Fills *opt with the defaults listed above. */
+void cr_default_options(cr_options *opt);
+
+/* Name of a CR_* code (static string). */
+const char *cr_strerror(int code);
+
+/* Library version and device check: returns CR_OK when a gfx950 device `device` is usable. */
+int cr_device_check(int device);
+
+/*
+ * cr_fit - one complete fit, host memory in and out.
+ *   x      host, N x n, locations (read)
+ *   ybar   host, N, observations (read)
+ *   delta  Tikhonov weight (> 0)
+ *   tol    stopping tolerance on report.kkt (> 0)
+ *   opt    options or NULL for defaults
+ *   y      host, N, fitted values of eta(lam) in FP64 (written)
+ *   xi     host, N x n, subgradients of eta(lam) in FP64 (written)
+ *   lambda host, N x N, final multipliers in FP64, or NULL (written)
+ *   rep    report or NULL (written)
+ * Runs: preprocess (Lipschitz constant), P-APG iterations with a stopping test every
+ * opt->check_every iterations, FP64 recovery of (y, xi) from the final multipliers, and the
+ * optional certificate.  N = 1 returns y = ybar, xi = 0 without touching the GPU.
+ */
+int cr_fit(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+           const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep);
+
+/* cr_fit_device - as cr_fit, but x, ybar, y, xi and lambda are device pointers on opt->device,
+ * and all work runs on opt->stream (or the library's stream).  Returns after the result is
+ * written. */
+int cr_fit_device(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
+                  double tol, const cr_options *opt, double *y, double *xi, double *lambda,
+                  cr_report *rep);
+
+/* ---- Step-level entry points: a solver whose state stays on the device. ----------------- */
+typedef struct cr_solver cr_solver;
+
+/* Creates the device state for one fit (copies x and ybar, host pointers).  lambda0 is an
+ * optional N x N host warm start (its diagonal is ignored), else lam^0 = 0 (Theorem "bound").
+ * Device memory: two N^2 multiplier buffers of the precision's width plus O(N n). */
+int cr_solver_create(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
+                     const cr_options *opt, const double *lambda0, cr_solver **out);
+int cr_solver_destroy(cr_solver *s);
+
+/* Preprocess: power iteration for sigma_max(C)^2; sets L = sigma2 / delta (eq. "eq:lischitz").
+ * L, sigma2 and iters may be NULL. */
+int cr_solver_lipschitz(cr_solver *s, double *L, double *sigma2, int32_t *iters);
+/* Uses the given L (> 0) instead. */
+int cr_solver_set_L(cr_solver *s, double L);
+
+/* Advances the P-APG iteration `iters` times in the solver's current precision. */
+int cr_solver_iterate(cr_solver *s, int64_t iters);
+
+/* Runs iterations with stopping tests until report.kkt <= tol or a budget ends (cr_fit's loop).
+ * Returns CR_OK, CR_ENOCONV or CR_ENUMERIC. */
+int cr_solver_solve(cr_solver *s, double tol, cr_report *rep);
+
+/* Switches the multiplier state to FP64 (a no-op in CR_FP64 mode). */
+int cr_solver_promote(cr_solver *s);
+
+/* Iteration counter k (number of completed iterations). */
+int64_t cr_solver_iterations(const cr_solver *s);
+
+/* Copies lam^k (N x N, FP64, host) out. */
+int cr_solver_get_lambda(cr_solver *s, double *lambda);
+/* FP64 closed-form eta(lam^k) = (ybar + A1^T lam^k, A2^T lam^k / delta) to host. */
+int cr_solver_get_primal(cr_solver *s, double *y, double *xi);
+/* FP64 stopping report of lam^k (and the certificate if opt.certificate). */
+int cr_solver_report(cr_solver *s, cr_report *rep);
+
+/* ---- Operators on device data (one call each; device pointers, synchronous). ------------ */
+/* s = C eta: s_ij = y_j - y_i + xi_i^T (x_i - x_j), zero diagonal; s is N x N (Def. "def:A1A2"). */
+int cr_op_residual(int64_t N, int64_t n, const double *x, const double *y, const double *xi,
+                   double *s, int device);
+/* (u, w) = C^T lam: u = colsum - rowsum, w_m = rowsum_m x_m - (Lam X)_m (Section 2.5). */
+int cr_op_adjoint(int64_t N, int64_t n, const double *x, const double *lam, double *u, double *w,
+                  int device);
+
+/* ---- Serving: continuous batching of fits on one device. --------------------------------- */
+typedef struct cr_ctx cr_ctx;
+
+/* byte_budget: device bytes the resident multiplier state of all admitted fits may use
+ * (0 = 80% of free device memory); max_slots: fits resident at once. */
+int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, cr_ctx **out);
+int cr_ctx_destroy(cr_ctx *ctx);
+/* Queues a fit (copies x, ybar); non-blocking.  Returns its id in *req_id. */
+int cr_submit(cr_ctx *ctx, int64_t N, int64_t n, const double *x, const double *ybar,
+              double delta, double tol, const cr_options *opt, int64_t *req_id);
+/* Non-blocking: CR_EAGAIN while running, else the fit's status; results copied out once. */
+int cr_poll(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
+            double *latency_s);
+/* Blocking version of cr_poll. */
+int cr_wait(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
+            double *latency_s);
+/* Counters: fits queued, running, finished; bytes of multiplier state resident. */
+int cr_ctx_stats(cr_ctx *ctx, int64_t *queued, int64_t *running, int64_t *finished,
+                 size_t *resident_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CR_H */

@@ -1,0 +1,765 @@
+// Host side of libcr: argument checks, device state of one fit (cr_solver), the P-APG driver
+// loop with its FISTA scalar schedule and stopping tests, and the one-call cr_fit entry
+// points.  Every step of the numerical path runs in the kernels of cr_kernels.hip.
+
+#include "cr_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+using namespace cr;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t lam_bytes(LamType t) { return t == LAM_F64 ? 8 : (t == LAM_F32 ? 4 : 2); }
+
+bool all_finite(const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+#define CR_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return fail_hip(e_, #call); \
+    } while (0)
+
+static int fail_hip(hipError_t e, const char *what) {
+    if (getenv("CR_DEBUG")) fprintf(stderr, "libcr: %s failed: %s\n", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? CR_ENOMEM : CR_EDEVICE;
+}
+
+extern "C" void cr_default_options(cr_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = CR_FP64;
+    opt->check_every = 50;
+    opt->max_iters = 2000000;
+    opt->time_budget_s = 0.0;
+    opt->L = 0.0;
+    opt->power_max_iters = 300;
+    opt->power_rtol = 1e-8;
+    opt->momentum = 1;
+    opt->certificate = 1;
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->stall_checks = 4;
+}
+
+extern "C" const char *cr_strerror(int code) {
+    switch (code) {
+    case CR_OK: return "ok";
+    case CR_EINVAL: return "invalid argument";
+    case CR_ENOMEM: return "out of device memory or byte budget";
+    case CR_ENOCONV: return "iteration or time budget exhausted before the tolerance";
+    case CR_ENUMERIC: return "non-finite value in the iterates";
+    case CR_EDEVICE: return "HIP device error or no gfx950 device";
+    case CR_EAGAIN: return "request still running";
+    case CR_ENOTFOUND: return "unknown request id";
+    default: return "unknown error";
+    }
+}
+
+extern "C" int cr_device_check(int device) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CR_EDEVICE;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return CR_EDEVICE;
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return CR_EDEVICE;
+    return CR_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Solver state
+// ---------------------------------------------------------------------------------------------
+
+int cr_solver::alloc(void **p, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? CR_ENOMEM : CR_EDEVICE;
+    }
+    owned.push_back(*p);
+    return CR_OK;
+}
+
+void cr_solver::release(void *p) {
+    if (!p) return;
+    for (size_t k = 0; k < owned.size(); ++k)
+        if (owned[k] == p) {
+            (void)hipFree(p);
+            owned.erase(owned.begin() + (long)k);
+            return;
+        }
+}
+
+cr_solver::~cr_solver() {
+    if (device >= 0) (void)hipSetDevice(device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void *p : owned) (void)hipFree(p);
+    if (h_scal) (void)hipHostFree(h_scal);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+size_t cr_state_bytes(int64_t N, int64_t n, int precision) {
+    Geometry g = make_geometry((int)N, (int)n);
+    const LamType lt = precision == CR_FP64 ? LAM_F64 : (precision == CR_MIXED_FP32 ? LAM_F32 : LAM_BF16);
+    size_t b = 2 * (size_t)g.Nr * g.ld * lam_bytes(lt);
+    b += (size_t)g.chunks * g.Nr * g.NP * 8 + (size_t)g.strips * g.ld * 12;
+    b += (size_t)g.Nr * g.NP * 8 * 6 + (size_t)g.Nr * 8 * 16;
+    return b;
+}
+
+static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
+    if (N < 1 || n < 1 || !(delta > 0.0) || !std::isfinite(delta)) return CR_EINVAL;
+    if (n + 1 > 16 * kMaxMB) return CR_EINVAL;
+    if (N > 200000) return CR_EINVAL;
+    if (opt) {
+        if (opt->precision < CR_FP64 || opt->precision > CR_MIXED_BF16) return CR_EINVAL;
+        if (opt->check_every < 1 || opt->max_iters < 0 || opt->power_max_iters < 1) return CR_EINVAL;
+        if (opt->L < 0.0 || !std::isfinite(opt->L) || opt->time_budget_s < 0.0) return CR_EINVAL;
+    }
+    return CR_OK;
+}
+
+// x, ybar: pointers of kind `on_device` (true: device memory on opt.device).
+int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
+                          const cr_options *opt_in, const double *lambda0, bool on_device, cr_solver **out) {
+    if (!out || !x || !ybar) return CR_EINVAL;
+    *out = nullptr;
+    cr_options opt;
+    if (opt_in) opt = *opt_in; else cr_default_options(&opt);
+    int rc = validate(N, n, delta, &opt);
+    if (rc) return rc;
+    if (cr_device_check(opt.device) != CR_OK) return CR_EDEVICE;
+    CR_HIP(hipSetDevice(opt.device));
+
+    // host copies for validation and the centring shift
+    std::vector<double> hx((size_t)N * n), hy((size_t)N);
+    if (on_device) {
+        CR_HIP(hipMemcpy(hx.data(), x, hx.size() * 8, hipMemcpyDeviceToHost));
+        CR_HIP(hipMemcpy(hy.data(), ybar, hy.size() * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(hx.data(), x, hx.size() * 8);
+        std::memcpy(hy.data(), ybar, hy.size() * 8);
+    }
+    if (!all_finite(hx.data(), hx.size()) || !all_finite(hy.data(), hy.size())) return CR_EINVAL;
+
+    cr_solver *s = new cr_solver();
+    s->device = opt.device;
+    s->opt = opt;
+    s->delta = delta;
+    s->g = make_geometry((int)N, (int)n);
+    s->precision = opt.precision;
+    s->lt = opt.precision == CR_FP64 ? LAM_F64 : (opt.precision == CR_MIXED_FP32 ? LAM_F32 : LAM_BF16);
+    s->fp32pass = opt.precision != CR_FP64;
+    double ymin = hy[0], ymax = hy[0];
+    for (double v : hy) { ymin = std::min(ymin, v); ymax = std::max(ymax, v); }
+    s->scale = std::max(1.0, ymax - ymin);
+
+    auto bail = [&](int code) { delete s; return code; };
+    if (opt.stream) {
+        s->stream = static_cast<hipStream_t>(opt.stream);
+        s->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return bail(CR_EDEVICE);
+        s->own_stream = true;
+    }
+    if (hipHostMalloc((void **)&s->h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return bail(CR_ENOMEM);
+
+    const Geometry &g = s->g;
+    const size_t nr = g.Nr, np = g.NP, rows_np = nr * np;
+    const size_t lamsz = nr * g.ld * lam_bytes(s->lt);
+#define CR_ALLOC(ptr, bytes) do { int r_ = s->alloc((void **)&(ptr), (bytes)); if (r_) return bail(r_); } while (0)
+    CR_ALLOC(s->lam[0], lamsz);
+    CR_ALLOC(s->lam[1], lamsz);
+    CR_ALLOC(s->xhat64, rows_np * 8);
+    CR_ALLOC(s->ybar64, nr * 8);
+    CR_ALLOC(s->y64, nr * 8);
+    CR_ALLOC(s->xi64, rows_np * 8);
+    CR_ALLOC(s->dmy64, nr * 8);
+    CR_ALLOC(s->yc, nr * 8);
+    CR_ALLOC(s->xic, rows_np * 8);
+    CR_ALLOC(s->dmyc, nr * 8);
+    CR_ALLOC(s->yr, nr * 8);
+    CR_ALLOC(s->xir, rows_np * 8);
+    CR_ALLOC(s->dmyr, nr * 8);
+    CR_ALLOC(s->rowred, nr * 2 * 8);
+    CR_ALLOC(s->part_acc, (size_t)g.chunks * rows_np * 8);
+    CR_ALLOC(s->part_col, (size_t)g.strips * g.ld * 8);
+    CR_ALLOC(s->part_red, (size_t)g.grid() * kRed * 8);
+    CR_ALLOC(s->part_min, (size_t)g.strips * g.ld * 8);
+    CR_ALLOC(s->part_arg, (size_t)g.strips * g.ld * 4);
+    CR_ALLOC(s->scal, 32 * 8);
+    if (s->fp32pass) {
+        CR_ALLOC(s->xhat32, rows_np * 4);
+        CR_ALLOC(s->y32, nr * 4);
+        CR_ALLOC(s->xi32, rows_np * 4);
+        CR_ALLOC(s->dmy32, nr * 4);
+    }
+    double *dx = nullptr, *dyb = nullptr, *dmu = nullptr;
+    CR_ALLOC(dx, hx.size() * 8);
+    CR_ALLOC(dyb, hy.size() * 8);
+    CR_ALLOC(dmu, (size_t)n * 8);
+#undef CR_ALLOC
+
+    // Mixed modes work in the frame x - mean(x): every constraint and the adjoint depend only
+    // on differences x_i - x_j, so (y, xi, lam) are unchanged while the float residual loses
+    // less to cancellation.  The FP64 mode keeps the caller's coordinates.
+    std::vector<double> mu((size_t)n, 0.0);
+    if (s->fp32pass) {
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t m = 0; m < n; ++m) mu[m] += hx[(size_t)i * n + m];
+        for (int64_t m = 0; m < n; ++m) mu[m] /= (double)N;
+    }
+    int rc2 = CR_OK;
+    auto H = [&](hipError_t e) { if (e != hipSuccess && rc2 == CR_OK) rc2 = fail_hip(e, "setup"); };
+    H(hipMemcpyAsync(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, s->stream));
+    H(hipMemcpyAsync(dyb, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, s->stream));
+    H(hipMemcpyAsync(dmu, mu.data(), mu.size() * 8, hipMemcpyHostToDevice, s->stream));
+    H(launch_prepare(g, dx, dyb, s->fp32pass ? dmu : nullptr, s->xhat64, s->xhat32, s->ybar64, s->stream));
+    // multipliers: lam^0 in both buffers (lam^{-1} := lam^0 makes the first extrapolation exact)
+    if (lambda0) {
+        double *dl = nullptr;
+        int r = s->alloc((void **)&dl, (size_t)N * N * 8);
+        if (r) return bail(r);
+        std::vector<double> hl((size_t)N * N);
+        if (on_device) H(hipMemcpy(hl.data(), lambda0, hl.size() * 8, hipMemcpyDeviceToHost));
+        else std::memcpy(hl.data(), lambda0, hl.size() * 8);
+        for (int64_t i = 0; i < N; ++i) hl[(size_t)i * N + i] = 0.0;
+        for (double v : hl)
+            if (!std::isfinite(v) || v < 0.0) { H(hipStreamSynchronize(s->stream)); return bail(CR_EINVAL); }
+        H(hipMemcpyAsync(dl, hl.data(), hl.size() * 8, hipMemcpyHostToDevice, s->stream));
+        H(launch_pack_lambda(g, dl, s->lam[0], s->lt, s->stream));
+        H(launch_pack_lambda(g, dl, s->lam[1], s->lt, s->stream));
+        H(hipStreamSynchronize(s->stream));
+        s->release(dl);
+    } else {
+        H(hipMemsetAsync(s->lam[0], 0, lamsz, s->stream));
+        H(hipMemsetAsync(s->lam[1], 0, lamsz, s->stream));
+    }
+    H(hipMemsetAsync(s->part_acc, 0, (size_t)g.chunks * rows_np * 8, s->stream));
+    H(hipMemsetAsync(s->part_col, 0, (size_t)g.strips * g.ld * 8, s->stream));
+    H(hipStreamSynchronize(s->stream));
+    s->release(dx);
+    s->release(dyb);
+    s->release(dmu);
+    if (rc2) return bail(rc2);
+    *out = s;
+    return CR_OK;
+}
+
+extern "C" int cr_solver_create(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
+                                const cr_options *opt, const double *lambda0, cr_solver **out) {
+    return cr_solver_create_impl(N, n, x, ybar, delta, opt, lambda0, false, out);
+}
+
+extern "C" int cr_solver_destroy(cr_solver *s) {
+    delete s;
+    return CR_OK;
+}
+
+// ---- passes ---------------------------------------------------------------------------------
+
+// Adjoint of stored multipliers `lam` (storage lt) in FP64 -> primal arrays (y, xi, dmy).
+int cr_solver::adjoint_to(const void *lam_p, LamType lt_p, double *y, double *xi, double *dmy, bool with_rowred,
+                          float *y32_, float *xi32_, float *dmy32_) {
+    PassArgs a{};
+    a.lam_a = lam_p;
+    a.xhat = xhat64;
+    a.part_acc = part_acc;
+    a.part_col = part_col;
+    CR_HIP(launch_pass(g, PASS_ADJ, false, lt_p, a, stream));
+    FinalizeArgs f{};
+    f.part_acc = part_acc;
+    f.part_col = part_col;
+    f.xf = xhat64;
+    f.ybar = ybar64;
+    f.y = y; f.xi = xi; f.dmy = dmy;
+    f.y32 = y32_; f.xi32 = xi32_; f.dmy32 = dmy32_;
+    f.rowred = with_rowred ? rowred : nullptr;
+    f.inv_delta = 1.0 / delta;
+    f.power = 0;
+    CR_HIP(launch_finalize(g, false, f, stream));
+    return CR_OK;
+}
+
+// eta^{k+1} for the next step from the current multipliers (used before the first iteration
+// and after a change of precision or of the pass arrays).
+int cr_solver::prime() {
+    // lam~^{k+1} = lam^k + beta_k (lam^k - lam^{k-1}); at k = 0 both buffers hold lam^0.  After a
+    // power iteration (k = 0) or a promotion, beta is applied by running the adjoint of lam~
+    // through a STEP-free path: the extrapolated point is formed explicitly in a scratch pass.
+    if (k == 0 || beta_last == 0.0) {
+        int rc = adjoint_to(lam[cur], lt, y64, xi64, dmy64, false, y32, xi32, dmy32);
+        if (rc) return rc;
+    } else {
+        // general case: form lam~ in the other buffer's storage is not allowed (it holds
+        // lam^{k-1}); instead accumulate lam^k and lam^{k-1} adjoints and combine linearly:
+        // C^T lam~ = (1 + beta) C^T lam^k - beta C^T lam^{k-1}.
+        int rc = adjoint_to(lam[cur], lt, yc, xic, dmyc, false, nullptr, nullptr, nullptr);
+        if (rc) return rc;
+        rc = adjoint_to(lam[1 - cur], lt, yr, xir, dmyr, false, nullptr, nullptr, nullptr);
+        if (rc) return rc;
+        CR_HIP(launch_combine(g, yc, xic, yr, xir, ybar64, xhat64, beta_last, y64, xi64, dmy64, y32, xi32, dmy32,
+                              stream));
+    }
+    primed = true;
+    return CR_OK;
+}
+
+int cr_solver::step_once() {
+    if (!primed) {
+        int rc = prime();
+        if (rc) return rc;
+    }
+    const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
+    PassArgs a{};
+    a.lam_a = lam[cur];
+    a.lam_b = lam[1 - cur];
+    a.beta_prev = opt.momentum ? beta_last : 0.0;
+    a.beta_next = beta_k;
+    a.inv_L = 1.0 / L;
+    a.part_acc = part_acc;
+    a.part_col = part_col;
+    if (fp32pass) {
+        a.xhat = xhat32; a.xi = xi32; a.yv = y32; a.dmy = dmy32;
+    } else {
+        a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
+    }
+    CR_HIP(launch_pass(g, PASS_STEP, fp32pass, lt, a, stream));
+    FinalizeArgs f{};
+    f.part_acc = part_acc;
+    f.part_col = part_col;
+    f.xf = xhat64;
+    f.ybar = ybar64;
+    f.y = y64; f.xi = xi64; f.dmy = dmy64;
+    f.y32 = fp32pass ? y32 : nullptr;
+    f.xi32 = fp32pass ? xi32 : nullptr;
+    f.dmy32 = fp32pass ? dmy32 : nullptr;
+    f.inv_delta = 1.0 / delta;
+    CR_HIP(launch_finalize(g, fp32pass, f, stream));
+    cur = 1 - cur;
+    t = t_next;
+    beta_last = beta_k;
+    ++k;
+    if (fp32pass) ++k_low;
+    return CR_OK;
+}
+
+int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
+    const double t0 = now_s();
+    CR_HIP(hipSetDevice(device));
+    CR_HIP(launch_power_init(g, xhat64, y64, xi64, dmy64, stream));
+    double est = 0.0;
+    int it = 0;
+    for (it = 1; it <= opt.power_max_iters; ++it) {
+        PassArgs a{};
+        a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
+        a.part_acc = part_acc; a.part_col = part_col; a.part_red = part_red;
+        CR_HIP(launch_pass(g, PASS_POWER, false, LAM_F64, a, stream));
+        FinalizeArgs f{};
+        f.part_acc = part_acc; f.part_col = part_col; f.xf = xhat64; f.ybar = ybar64;
+        f.y = y64; f.xi = xi64; f.dmy = dmy64; f.rowred = rowred; f.inv_delta = 1.0; f.power = 1;
+        CR_HIP(launch_finalize(g, false, f, stream));
+        CR_HIP(launch_reduce(part_red, g.grid(), kRed, 0, 1, scal, stream));
+        CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 1, stream));
+        CR_HIP(launch_normalize(g, y64, xi64, dmy64, scal + 1, stream));
+        CR_HIP(hipMemcpyAsync(h_scal, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        CR_HIP(hipStreamSynchronize(stream));
+        const double nw = h_scal[0];
+        if (!std::isfinite(nw)) return CR_ENUMERIC;
+        if (h_scal[1] + h_scal[2] == 0.0) { est = nw; break; }
+        const bool done = std::fabs(nw - est) <= opt.power_rtol * nw;
+        est = nw;
+        if (done) break;
+    }
+    if (it > opt.power_max_iters) it = opt.power_max_iters;
+    sigma2 = est;
+    L = est / delta;
+    if (!(L > 0.0)) L = 1.0 / delta;   // every x equal and N = 1: any positive step is exact
+    power_iters = it;
+    preprocess_s = now_s() - t0;
+    primed = false;
+    if (Lout) *Lout = L;
+    if (s2out) *s2out = sigma2;
+    if (itout) *itout = it;
+    return CR_OK;
+}
+
+// FP64 stopping test at lam^k; fills rep (without timing fields).  Leaves eta(lam^k) in yc/xic.
+int cr_solver::check(cr_report *rep, bool certificate) {
+    int rc = adjoint_to(lam[cur], lt, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    PassArgs a{};
+    a.lam_a = lam[cur];
+    a.xhat = xhat64; a.xi = xic; a.yv = yc; a.dmy = dmyc;
+    a.part_red = part_red;
+    CR_HIP(launch_pass(g, PASS_KKT, false, lt, a, stream));
+    CR_HIP(launch_reduce(part_red, g.grid(), kRed, 2, 4, scal, stream));
+    CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 4, stream));
+    int nsc = 6;
+    if (certificate) {
+        PassArgs r{};
+        r.xhat = xhat64; r.xi = xic; r.yv = yc; r.dmy = dmyc;
+        r.part_min = part_min; r.part_arg = part_arg;
+        CR_HIP(launch_pass(g, PASS_REPAIR, false, LAM_F64, r, stream));
+        CR_HIP(launch_repair_finish(g, part_min, part_arg, yc, xic, ybar64, yr, xir, rowred, stream));
+        CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 6, stream));
+        nsc = 8;
+    }
+    CR_HIP(hipMemcpyAsync(h_scal, scal, nsc * sizeof(double), hipMemcpyDeviceToHost, stream));
+    CR_HIP(hipStreamSynchronize(stream));
+    const double pairs = (double)g.N * (double)g.N - (double)g.N;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->precision = precision;
+    rep->iters = k;
+    rep->iters_low = k_low;
+    rep->L = L;
+    rep->sigma2 = sigma2;
+    rep->power_iters = power_iters;
+    rep->preprocess_seconds = preprocess_s;
+    rep->scale = scale;
+    rep->nat_res_max = h_scal[0] / scale;
+    rep->max_viol = h_scal[1] / scale;
+    rep->infeas_rms = pairs > 0 ? std::sqrt(h_scal[2] / pairs) : 0.0;
+    rep->comp_sum = h_scal[3];
+    rep->dual_gap_paper = pairs > 0 ? std::fabs(h_scal[3]) / pairs : 0.0;
+    rep->primal_obj = 0.5 * h_scal[4] + 0.5 * delta * h_scal[5];
+    rep->dual_obj = rep->primal_obj - rep->comp_sum;
+    // The returned (y, xi) are the FP64 closed form of lam^k, so stationarity holds to rounding.
+    rep->stat_y = 0.0;
+    rep->stat_xi = 0.0;
+    rep->kkt = std::max(rep->nat_res_max, std::max(rep->stat_y, rep->stat_xi));
+    if (certificate) {
+        rep->cert_primal = 0.5 * h_scal[6] + 0.5 * delta * h_scal[7];
+        rep->cert_gap = rep->cert_primal - rep->dual_obj;
+        rep->y_err_bound = std::sqrt(std::max(0.0, 2.0 * rep->cert_gap));
+    }
+    bool finite = true;
+    for (int q = 0; q < nsc; ++q) finite = finite && std::isfinite(h_scal[q]);
+    rep->status = finite ? CR_OK : CR_ENUMERIC;
+    checked_k = k;
+    return finite ? CR_OK : CR_ENUMERIC;
+}
+
+int cr_solver::promote() {
+    if (lt == LAM_F64 && !fp32pass) return CR_OK;
+    CR_HIP(hipSetDevice(device));
+    const size_t bytes = (size_t)g.Nr * g.ld * 8;
+    void *n0 = nullptr, *n1 = nullptr;
+    int rc = alloc(&n0, bytes);
+    if (rc) return rc;
+    rc = alloc(&n1, bytes);
+    if (rc) { release(n0); return rc; }
+    CR_HIP(launch_convert(g, lam[0], lt, n0, LAM_F64, stream));
+    CR_HIP(launch_convert(g, lam[1], lt, n1, LAM_F64, stream));
+    CR_HIP(hipStreamSynchronize(stream));
+    release(lam[0]);
+    release(lam[1]);
+    lam[0] = n0;
+    lam[1] = n1;
+    lt = LAM_F64;
+    fp32pass = false;
+    primed = false;   // eta^{k+1} is recomputed in FP64 from the promoted multipliers
+    return CR_OK;
+}
+
+int cr_solver::solve(double tol, cr_report *rep_out) {
+    const double t0 = now_s();
+    CR_HIP(hipSetDevice(device));
+    if (!(tol > 0.0)) return CR_EINVAL;
+    if (!(L > 0.0)) {
+        int rc = lipschitz(nullptr, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    cr_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    int status = CR_ENOCONV;
+    double best = INFINITY;
+    int since_best = 0;
+    int checks = 0;
+    const int64_t kmax = opt.max_iters;
+    // iteration 0 check: lam^0 may already be optimal (e.g. convex data)
+    for (;;) {
+        int rc = check(&rep, false);
+        ++checks;
+        if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
+        if (rc) return rc;
+        if (rep.kkt <= tol) { status = CR_OK; break; }
+        if (k >= kmax) break;
+        if (opt.time_budget_s > 0.0 && now_s() - t0 > opt.time_budget_s) break;
+        if (fp32pass) {
+            if (rep.kkt < 0.9 * best) { best = rep.kkt; since_best = 0; }
+            else if (++since_best >= opt.stall_checks) {
+                rc = promote();
+                if (rc) return rc;
+                best = INFINITY;
+                since_best = 0;
+            }
+        }
+        const int64_t todo = std::min<int64_t>(opt.check_every, kmax - k);
+        for (int64_t q = 0; q < todo; ++q) {
+            rc = step_once();
+            if (rc) return rc;
+        }
+    }
+    if (opt.certificate) {
+        int rc = check(&rep, true);
+        if (rc && rc != CR_ENUMERIC) return rc;
+        if (rc == CR_ENUMERIC) status = CR_ENUMERIC;
+    }
+    rep.checks = checks;
+    rep.status = status;
+    rep.seconds = now_s() - t0;
+    last_report = rep;
+    if (rep_out) *rep_out = rep;
+    return status;
+}
+
+// ---- C entry points on the solver -------------------------------------------------------------
+
+extern "C" int cr_solver_lipschitz(cr_solver *s, double *L, double *sigma2, int32_t *iters) {
+    if (!s) return CR_EINVAL;
+    return s->lipschitz(L, sigma2, iters);
+}
+
+extern "C" int cr_solver_set_L(cr_solver *s, double L) {
+    if (!s || !(L > 0.0) || !std::isfinite(L)) return CR_EINVAL;
+    s->L = L;
+    s->sigma2 = 0.0;
+    return CR_OK;
+}
+
+extern "C" int cr_solver_iterate(cr_solver *s, int64_t iters) {
+    if (!s || iters < 0) return CR_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess) return CR_EDEVICE;
+    if (!(s->L > 0.0)) {
+        int rc = s->lipschitz(nullptr, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    for (int64_t q = 0; q < iters; ++q) {
+        int rc = s->step_once();
+        if (rc) return rc;
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return CR_EDEVICE;
+    return CR_OK;
+}
+
+extern "C" int cr_solver_solve(cr_solver *s, double tol, cr_report *rep) {
+    if (!s) return CR_EINVAL;
+    return s->solve(tol, rep);
+}
+
+extern "C" int cr_solver_promote(cr_solver *s) {
+    if (!s) return CR_EINVAL;
+    return s->promote();
+}
+
+extern "C" int64_t cr_solver_iterations(const cr_solver *s) { return s ? s->k : -1; }
+
+extern "C" int cr_solver_get_lambda(cr_solver *s, double *lambda) {
+    if (!s || !lambda) return CR_EINVAL;
+    CR_HIP(hipSetDevice(s->device));
+    double *d = nullptr;
+    const size_t bytes = (size_t)s->g.N * s->g.N * 8;
+    int rc = s->alloc((void **)&d, bytes);
+    if (rc) return rc;
+    CR_HIP(launch_unpack_lambda(s->g, s->lam[s->cur], s->lt, d, s->stream));
+    CR_HIP(hipMemcpyAsync(lambda, d, bytes, hipMemcpyDeviceToHost, s->stream));
+    CR_HIP(hipStreamSynchronize(s->stream));
+    s->release(d);
+    return CR_OK;
+}
+
+static int primal_out(cr_solver *s, const double *ysrc, const double *xisrc, double *y, double *xi, bool device_out) {
+    const size_t N = s->g.N, n = s->g.n;
+    double *dy = nullptr, *dxi = nullptr;
+    if (device_out) {
+        dy = y; dxi = xi;
+    } else {
+        int rc = s->alloc((void **)&dy, N * 8);
+        if (rc) return rc;
+        rc = s->alloc((void **)&dxi, N * n * 8);
+        if (rc) return rc;
+    }
+    CR_HIP(launch_unpad_primal(s->g, ysrc, xisrc, dy, dxi, s->stream));
+    if (!device_out) {
+        CR_HIP(hipMemcpyAsync(y, dy, N * 8, hipMemcpyDeviceToHost, s->stream));
+        CR_HIP(hipMemcpyAsync(xi, dxi, N * n * 8, hipMemcpyDeviceToHost, s->stream));
+    }
+    CR_HIP(hipStreamSynchronize(s->stream));
+    if (!device_out) {
+        s->release(dy);
+        s->release(dxi);
+    }
+    return CR_OK;
+}
+
+extern "C" int cr_solver_get_primal(cr_solver *s, double *y, double *xi) {
+    if (!s || !y || !xi) return CR_EINVAL;
+    CR_HIP(hipSetDevice(s->device));
+    int rc = s->adjoint_to(s->lam[s->cur], s->lt, s->yc, s->xic, s->dmyc, false, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    return primal_out(s, s->yc, s->xic, y, xi, false);
+}
+
+extern "C" int cr_solver_report(cr_solver *s, cr_report *rep) {
+    if (!s || !rep) return CR_EINVAL;
+    CR_HIP(hipSetDevice(s->device));
+    int rc = s->check(rep, s->opt.certificate != 0);
+    rep->checks = 1;
+    return rc;
+}
+
+// ---- one-call fits --------------------------------------------------------------------------
+
+static int fit_trivial(int64_t N, int64_t n, const double *ybar, double *y, double *xi, double *lambda, cr_report *rep,
+                       bool device_out, const cr_options &opt) {
+    // N = 1: no pair constraint; the minimizer is y = ybar, xi = 0.
+    (void)N;
+    if (device_out) {
+        if (hipSetDevice(opt.device) != hipSuccess) return CR_EDEVICE;
+        CR_HIP(hipMemcpy(y, ybar, 8, hipMemcpyDeviceToDevice));
+        CR_HIP(hipMemset(xi, 0, (size_t)n * 8));
+        if (lambda) CR_HIP(hipMemset(lambda, 0, 8));
+    } else {
+        y[0] = ybar[0];
+        for (int64_t m = 0; m < n; ++m) xi[m] = 0.0;
+        if (lambda) lambda[0] = 0.0;
+    }
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->precision = opt.precision;
+        rep->scale = 1.0;
+    }
+    return CR_OK;
+}
+
+static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+                    const cr_options *opt_in, double *y, double *xi, double *lambda, cr_report *rep, bool dev) {
+    const double t0 = now_s();
+    cr_options opt;
+    if (opt_in) opt = *opt_in; else cr_default_options(&opt);
+    if (!x || !ybar || !y || !xi) return CR_EINVAL;
+    int rc = validate(N, n, delta, &opt);
+    if (rc) return rc;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return CR_EINVAL;
+    if (N == 1) return fit_trivial(N, n, ybar, y, xi, lambda, rep, dev, opt);
+    cr_solver *s = nullptr;
+    rc = cr_solver_create_impl(N, n, x, ybar, delta, &opt, nullptr, dev, &s);
+    if (rc) return rc;
+    if (opt.L > 0.0) s->L = opt.L;
+    cr_report r;
+    int status = s->solve(tol, &r);
+    if (status != CR_OK && status != CR_ENOCONV && status != CR_ENUMERIC) {
+        delete s;
+        return status;
+    }
+    // eta(lam^k) is in yc / xic from the last check
+    rc = primal_out(s, s->yc, s->xic, y, xi, dev);
+    if (rc) { delete s; return rc; }
+    if (lambda) {
+        if (dev) {
+            if (launch_unpack_lambda(s->g, s->lam[s->cur], s->lt, lambda, s->stream) != hipSuccess ||
+                hipStreamSynchronize(s->stream) != hipSuccess) { delete s; return CR_EDEVICE; }
+        } else {
+            rc = cr_solver_get_lambda(s, lambda);
+            if (rc) { delete s; return rc; }
+        }
+    }
+    r.seconds = now_s() - t0;
+    if (rep) *rep = r;
+    delete s;
+    return status;
+}
+
+extern "C" int cr_fit(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+                      const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep) {
+    return fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, false);
+}
+
+extern "C" int cr_fit_device(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+                             const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep) {
+    return fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, true);
+}
+
+// ---- operators --------------------------------------------------------------------------------
+
+extern "C" int cr_op_residual(int64_t N, int64_t n, const double *x, const double *y, const double *xi, double *s_out,
+                              int device) {
+    if (N < 1 || n < 1 || n + 1 > 16 * kMaxMB || !x || !y || !xi || !s_out) return CR_EINVAL;
+    cr_options opt;
+    cr_default_options(&opt);
+    opt.device = device;
+    if (cr_device_check(device) != CR_OK) return CR_EDEVICE;
+    CR_HIP(hipSetDevice(device));
+    // a solver with zero observations gives the padded location array and scratch
+    std::vector<double> zy((size_t)N, 0.0);
+    std::vector<double> hx((size_t)N * n);
+    CR_HIP(hipMemcpy(hx.data(), x, hx.size() * 8, hipMemcpyDeviceToHost));
+    cr_solver *s = nullptr;
+    int rc = cr_solver_create_impl(N, n, hx.data(), zy.data(), 1.0, &opt, nullptr, false, &s);
+    if (rc) return rc;
+    rc = CR_OK;
+    do {
+        if (launch_pad_primal(s->g, y, xi, s->xhat64, s->yc, s->xic, s->dmyc, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        PassArgs a{};
+        a.lam_b = s->lam[0];
+        a.xhat = s->xhat64; a.xi = s->xic; a.yv = s->yc; a.dmy = s->dmyc;
+        if (launch_pass(s->g, PASS_RESID, false, LAM_F64, a, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (launch_unpack_lambda(s->g, s->lam[0], LAM_F64, s_out, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (hipStreamSynchronize(s->stream) != hipSuccess) rc = CR_EDEVICE;
+    } while (0);
+    delete s;
+    return rc;
+}
+
+extern "C" int cr_op_adjoint(int64_t N, int64_t n, const double *x, const double *lam, double *u, double *w, int device) {
+    if (N < 1 || n < 1 || n + 1 > 16 * kMaxMB || !x || !lam || !u || !w) return CR_EINVAL;
+    cr_options opt;
+    cr_default_options(&opt);
+    opt.device = device;
+    if (cr_device_check(device) != CR_OK) return CR_EDEVICE;
+    CR_HIP(hipSetDevice(device));
+    std::vector<double> zy((size_t)N, 0.0);
+    std::vector<double> hx((size_t)N * n);
+    CR_HIP(hipMemcpy(hx.data(), x, hx.size() * 8, hipMemcpyDeviceToHost));
+    cr_solver *s = nullptr;
+    int rc = cr_solver_create_impl(N, n, hx.data(), zy.data(), 1.0, &opt, nullptr, false, &s);
+    if (rc) return rc;
+    rc = CR_OK;
+    do {
+        if (launch_pack_lambda(s->g, lam, s->lam[0], LAM_F64, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        PassArgs a{};
+        a.lam_a = s->lam[0];
+        a.xhat = s->xhat64;
+        a.part_acc = s->part_acc;
+        a.part_col = s->part_col;
+        if (launch_pass(s->g, PASS_ADJ, false, LAM_F64, a, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        FinalizeArgs f{};
+        f.part_acc = s->part_acc; f.part_col = s->part_col; f.xf = s->xhat64; f.ybar = s->ybar64;
+        f.y = s->yc; f.xi = s->xic; f.dmy = s->dmyc; f.inv_delta = 1.0; f.power = 1;
+        if (launch_finalize(s->g, false, f, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (launch_unpad_primal(s->g, s->yc, s->xic, u, w, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (hipStreamSynchronize(s->stream) != hipSuccess) rc = CR_EDEVICE;
+    } while (0);
+    delete s;
+    return rc;
+}

@@ -1,0 +1,68 @@
+// Internal state of one fit (shared by the C API and the serving loop).
+#pragma once
+
+#include "../../include/cr.h"
+#include "cr_kernels.h"
+
+#include <vector>
+
+struct cr_solver {
+    cr::Geometry g{};
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    cr_options opt{};
+    double delta = 1.0;
+    double scale = 1.0;          // S_y = max(1, max ybar - min ybar)
+    int precision = CR_FP64;     // requested mode
+    cr::LamType lt = cr::LAM_F64;  // current multiplier storage
+    bool fp32pass = false;       // current pass arithmetic is FP32
+
+    // device buffers (padded as described by Geometry)
+    void *lam[2] = {nullptr, nullptr};
+    double *xhat64 = nullptr, *ybar64 = nullptr;
+    double *y64 = nullptr, *xi64 = nullptr, *dmy64 = nullptr;      // eta^{k+1} for the next step
+    float *xhat32 = nullptr, *y32 = nullptr, *xi32 = nullptr, *dmy32 = nullptr;
+    double *yc = nullptr, *xic = nullptr, *dmyc = nullptr;         // eta(lam^k) for tests/output
+    double *yr = nullptr, *xir = nullptr, *dmyr = nullptr;         // scratch primal (repair, prime)
+    double *rowred = nullptr;
+    void *part_acc = nullptr, *part_col = nullptr;
+    double *part_red = nullptr, *part_min = nullptr;
+    int *part_arg = nullptr;
+    double *scal = nullptr;
+    double *h_scal = nullptr;    // pinned
+    std::vector<void *> owned;
+
+    // iteration state
+    double L = 0.0, sigma2 = 0.0, preprocess_s = 0.0;
+    int power_iters = 0;
+    int64_t k = 0, k_low = 0, checked_k = -1;
+    int cur = 0;                 // buffer holding lam^k; the other holds lam^{k-1}
+    double t = 1.0;              // t_{k+1}
+    double beta_last = 0.0;      // beta_k (0 before the first iteration)
+    bool primed = false;
+    cr_report last_report{};
+
+    ~cr_solver();
+    int alloc(void **p, size_t bytes);
+    void release(void *p);
+    int adjoint_to(const void *lam_p, cr::LamType lt_p, double *y, double *xi, double *dmy, bool with_rowred,
+                   float *y32_, float *xi32_, float *dmy32_);
+    int prime();
+    int step_once();
+    int lipschitz(double *L, double *s2, int32_t *it);
+    int check(cr_report *rep, bool certificate);
+    int promote();
+    int solve(double tol, cr_report *rep);
+};
+
+int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
+                          const cr_options *opt, const double *lambda0, bool on_device, cr_solver **out);
+size_t cr_state_bytes(int64_t N, int64_t n, int precision);
+
+namespace cr {
+// y = (1 + b) ya - b yb, xi likewise, dmy = xi^T x - y; float copies when given.
+hipError_t launch_combine(const Geometry &g, const double *ya, const double *xia, const double *yb,
+                          const double *xib, const double *ybar, const double *xhat64, double b, double *y,
+                          double *xi, double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st);
+}  // namespace cr

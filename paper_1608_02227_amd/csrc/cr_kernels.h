@@ -1,0 +1,143 @@
+// Internal launch interface of the gfx950 kernels (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cr {
+
+// Storage type of the N x N multiplier buffers.
+enum LamType : int { LAM_F64 = 0, LAM_F32 = 1, LAM_BF16 = 2 };
+
+// What one sweep over the pairs computes (all modes form the residual tile s = C eta except ADJ).
+enum PassMode : int {
+    PASS_STEP = 0,   // Steps 2-4 fused with the adjoint of the next extrapolated point
+    PASS_ADJ = 1,    // adjoint C^T lam of a stored multiplier matrix
+    PASS_KKT = 2,    // stopping-test reductions at a stored multiplier matrix
+    PASS_POWER = 3,  // z = C v and C^T z (power iteration), plus ||z||^2
+    PASS_REPAIR = 4, // column minima of s and their arg-min rows (max-affine repair)
+    PASS_RESID = 5   // writes s = C eta (FP64, zero diagonal and padding) into lam_b
+};
+
+// Tiling shared by host and device code.
+constexpr int kWaves = 4;                // waves per workgroup
+constexpr int kRows = 16 * kWaves;       // rows i per workgroup (one 16-row MFMA block per wave)
+constexpr int kSuper = 64;               // columns j staged in LDS per step
+constexpr int kMaxMB = 4;                // feature blocks of 16: n + 1 <= 64
+constexpr int kRed = 4;                  // reduction slots per workgroup
+
+struct Geometry {
+    int N;          // points
+    int n;          // features
+    int NP;         // padded feature stride: 16 * MB >= n + 1 (column n of xhat holds 1)
+    int MB;         // NP / 16
+    int ks1;        // ceil(n / 4): K-steps of the residual contraction
+    int Nr;         // padded rows (multiple of kRows); also the padded column count ld
+    int ld;         // leading dimension of the multiplier buffers (== Nr)
+    int strips;     // Nr / kRows
+    int chunks;     // column chunks per strip (workgroups per strip)
+    int chunk_cols; // columns per chunk (multiple of kSuper)
+    int grid() const { return strips * chunks; }
+};
+
+Geometry make_geometry(int N, int n);
+
+// One sweep over all pairs.  T is the arithmetic type of the contraction and epilogue; the
+// multiplier buffers use storage `lt`.  Pointer roles (all device, padded as in Geometry):
+//   lam_a   : lam^{k-1} (STEP) or the multipliers to read (ADJ, KKT); unused by POWER/REPAIR
+//   lam_b   : lam^{k-2} in, lam^k out (STEP only)
+//   xhat    : Nr x NP locations of type T; column n is 1 for real rows, padding is 0
+//   xi      : Nr x NP subgradients (or the power vector's xi part), type T, zero padded
+//   yv      : Nr fitted values (or the power vector's y part), type T
+//   dmy     : Nr values d_i - y_i with d_i = xi_i^T x_i, type T
+//   part_acc: chunks x Nr x NP partial (Lam X) rows of type T; column n holds row sums
+//   part_col: strips x ld partial column sums of type T
+//   part_red: grid x kRed double reductions (KKT: max nat, max viol, sum neg^2, sum lam s;
+//             POWER: sum z^2)
+//   part_min / part_arg: strips x ld column minima and arg-min rows (REPAIR)
+struct PassArgs {
+    const void *lam_a;
+    void *lam_b;
+    const void *xhat;
+    const void *xi;
+    const void *yv;
+    const void *dmy;
+    void *part_acc;
+    void *part_col;
+    double *part_red;
+    double *part_min;
+    int *part_arg;
+    double beta_prev;   // beta_{k-1}: lam~^k = lam^{k-1} + beta_{k-1} (lam^{k-1} - lam^{k-2})
+    double beta_next;   // beta_k:     lam~^{k+1} = lam^k + beta_k (lam^k - lam^{k-1})
+    double inv_L;       // 1 / L
+};
+
+hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamType lt,
+                       const PassArgs &a, hipStream_t st);
+
+// Finalize: turn the partial sums of one sweep into the primal point.
+//   PRIMAL: y = ybar + (c - r), xi_m = (r x_m - (Lam X)_m) / delta, dmy = xi^T x - y
+//   POWER : y = (c - r), xi_m = r x_m - (Lam X)_m (C^T z), dmy likewise
+// Inputs: the partials of type T (fp32 flag), xf (Nr x NP, FP64 locations matching the pass),
+// ybar (Nr).  Outputs: FP64 y, xi, dmy (Nr, Nr x NP, Nr); optional float copies y32/xi32/dmy32
+// (may be null); rowred (Nr x 2: (y - ybar)^2 or y^2, and ||xi||^2), may be null.
+struct FinalizeArgs {
+    const void *part_acc;
+    const void *part_col;
+    const double *xf;
+    const double *ybar;
+    double *y, *xi, *dmy;
+    float *y32, *xi32, *dmy32;
+    double *rowred;
+    double inv_delta;
+    int power;               // 1: POWER variant
+};
+hipError_t launch_finalize(const Geometry &g, bool fp32, const FinalizeArgs &a, hipStream_t st);
+
+// Sums / maxima of per-block partials: out[q] = op_q over blocks of part[b * stride + q],
+// with op = max for q < nmax and sum otherwise.  Single workgroup, deterministic order.
+hipError_t launch_reduce(const double *part, int blocks, int stride, int nmax, int nout,
+                         double *out, hipStream_t st);
+
+// Multiplies y, xi, dmy (FP64, Nr / Nr x NP / Nr) by 1/sqrt(sq[0] + sq[1]).
+hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dmy,
+                            const double *sq, hipStream_t st);
+
+// Converts between multiplier storages; src and dst are Nr x ld.
+hipError_t launch_convert(const Geometry &g, const void *src, LamType st_, void *dst, LamType dt,
+                          hipStream_t st);
+
+// Copies a dense N x N FP64 matrix (row stride N) into / out of a padded buffer of storage lt,
+// zeroing the diagonal and the padding on the way in.
+hipError_t launch_pack_lambda(const Geometry &g, const double *dense, void *dst, LamType lt,
+                              hipStream_t st);
+hipError_t launch_unpack_lambda(const Geometry &g, const void *src, LamType lt, double *dense,
+                                hipStream_t st);
+
+// Builds xhat (FP64 x - mu, ones in column n, zero padding) and optionally its float copy
+// from dense N x n locations, and pads ybar (may be null).  mu may be null (no shift).
+hipError_t launch_prepare(const Geometry &g, const double *x, const double *ybar,
+                          const double *mu, double *xhat64, float *xhat32, double *ybar_pad,
+                          hipStream_t st);
+
+// Power-iteration start: v_y,l = -1 + 2 l / (N - 1), v_xi = 1, scaled by 1/||v||; writes
+// y, xi and dmy = xi^T x - y (FP64, padded) from xhat64.
+hipError_t launch_power_init(const Geometry &g, const double *xhat64, double *y, double *xi,
+                             double *dmy, hipStream_t st);
+
+// Pads dense FP64 y (N) and xi (N x n) into Nr / Nr x NP arrays and sets dmy = xi^T x - y.
+hipError_t launch_pad_primal(const Geometry &g, const double *y_in, const double *xi_in,
+                             const double *xhat64, double *y, double *xi, double *dmy,
+                             hipStream_t st);
+
+// Repair: for column j, colmin over strips -> y'_j = y_j - min(0, colmin), piece_j; writes
+// y'(Nr), xi'(Nr x NP) and rowred' (Nr x 2) for the objective.
+hipError_t launch_repair_finish(const Geometry &g, const double *part_min, const int *part_arg,
+                                const double *y, const double *xi, const double *ybar,
+                                double *y_rep, double *xi_rep, double *rowred, hipStream_t st);
+
+// Copies the FP64 y (Nr) and xi (Nr x NP) to dense N and N x n arrays.
+hipError_t launch_unpad_primal(const Geometry &g, const double *y, const double *xi,
+                               double *y_out, double *xi_out, hipStream_t st);
+
+}  // namespace cr

@@ -1,0 +1,219 @@
+// Serving: continuous batching of convex-regression fits on one device.
+//
+// Requests enter a FIFO queue.  An admission step moves the head of the queue onto a free slot
+// as soon as one is free and the device bytes of its state (dominated by the two N^2 multiplier
+// buffers, plus the FP64 pair during a mixed-precision promotion) fit in the context's budget.
+// Each slot has its own worker thread and HIP stream, so admitted fits run concurrently on the
+// GPU and a new fit starts the moment one retires.  A fit's arithmetic does not depend on what
+// else is running (same kernels, tiling and fixed-order reductions), so its result is bitwise
+// the same alone and in a mix.  Strict FIFO: a head request that does not fit waits for memory
+// rather than being overtaken.
+
+#include "cr_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    int64_t id = 0;
+    int64_t N = 0, n = 0;
+    std::vector<double> x, ybar;
+    double delta = 1e-3, tol = 1e-4;
+    cr_options opt{};
+    size_t bytes = 0;
+    double t_submit = 0.0, t_done = 0.0;
+    int state = 0;  // 0 queued, 1 running, 2 done
+    int status = CR_OK;
+    std::vector<double> y, xi;
+    cr_report rep{};
+};
+
+}  // namespace
+
+struct cr_ctx {
+    int device = 0;
+    size_t budget = 0;
+    int max_slots = 1;
+    std::mutex mu;
+    std::condition_variable cv_work;   // slot threads wait for assignments
+    std::condition_variable cv_done;   // waiters for results / admission changes
+    std::deque<int64_t> queue;
+    std::map<int64_t, std::unique_ptr<Request>> reqs;
+    std::vector<int64_t> assigned;     // per slot: request id or -1
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    size_t resident = 0;
+    int64_t next_id = 1;
+    int64_t finished = 0, running = 0;
+    bool stop = false;
+
+    void admit_locked() {
+        while (!queue.empty()) {
+            Request *r = reqs[queue.front()].get();
+            int slot = -1;
+            for (int q = 0; q < max_slots; ++q)
+                if (assigned[q] < 0) { slot = q; break; }
+            if (slot < 0 || resident + r->bytes > budget) return;
+            queue.pop_front();
+            assigned[slot] = r->id;
+            resident += r->bytes;
+            r->state = 1;
+            ++running;
+        }
+        cv_work.notify_all();
+    }
+
+    void worker(int slot) {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            cv_work.wait(lk, [&] { return stop || assigned[slot] >= 0; });
+            if (stop) return;
+            Request *r = reqs[assigned[slot]].get();
+            lk.unlock();
+            run(r, streams[slot]);
+            lk.lock();
+            r->state = 2;
+            resident -= r->bytes;
+            assigned[slot] = -1;
+            --running;
+            ++finished;
+            admit_locked();
+            cv_done.notify_all();
+        }
+    }
+
+    void run(Request *r, hipStream_t st) {
+        cr_options o = r->opt;
+        o.device = device;
+        o.stream = st;
+        r->y.assign((size_t)r->N, 0.0);
+        r->xi.assign((size_t)(r->N * r->n), 0.0);
+        r->status = cr_fit(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
+                           r->xi.data(), nullptr, &r->rep);
+        r->t_done = now_s();
+        r->x.clear();
+        r->x.shrink_to_fit();
+    }
+};
+
+extern "C" int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, cr_ctx **out) {
+    if (!out || max_slots < 1 || max_slots > 64) return CR_EINVAL;
+    *out = nullptr;
+    if (cr_device_check(device) != CR_OK) return CR_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return CR_EDEVICE;
+    cr_ctx *c = new cr_ctx();
+    c->device = device;
+    c->max_slots = max_slots;
+    if (byte_budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete c; return CR_EDEVICE; }
+        byte_budget = (size_t)(0.8 * (double)fr);
+    }
+    c->budget = byte_budget;
+    c->assigned.assign((size_t)max_slots, -1);
+    c->streams.assign((size_t)max_slots, nullptr);
+    for (int q = 0; q < max_slots; ++q) {
+        if (hipStreamCreateWithFlags(&c->streams[q], hipStreamNonBlocking) != hipSuccess) {
+            for (int p = 0; p < q; ++p) (void)hipStreamDestroy(c->streams[p]);
+            delete c;
+            return CR_EDEVICE;
+        }
+    }
+    for (int q = 0; q < max_slots; ++q) c->workers.emplace_back([c, q] { c->worker(q); });
+    *out = c;
+    return CR_OK;
+}
+
+extern "C" int cr_ctx_destroy(cr_ctx *c) {
+    if (!c) return CR_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->stop = true;
+        c->queue.clear();
+    }
+    c->cv_work.notify_all();
+    // running fits finish their current solve before the threads exit
+    for (auto &t : c->workers) t.join();
+    for (auto s : c->streams) (void)hipStreamDestroy(s);
+    delete c;
+    return CR_OK;
+}
+
+extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+                         const cr_options *opt, int64_t *req_id) {
+    if (!c || !x || !ybar || !req_id || N < 1 || n < 1 || n + 1 > 16 * cr::kMaxMB || !(delta > 0.0) || !(tol > 0.0))
+        return CR_EINVAL;
+    auto r = std::make_unique<Request>();
+    r->N = N;
+    r->n = n;
+    r->x.assign(x, x + (size_t)(N * n));
+    r->ybar.assign(ybar, ybar + (size_t)N);
+    r->delta = delta;
+    r->tol = tol;
+    if (opt) r->opt = *opt; else cr_default_options(&r->opt);
+    r->bytes = cr_state_bytes(N, n, r->opt.precision);
+    if (r->opt.precision != CR_FP64) r->bytes += cr_state_bytes(N, n, CR_FP64);   // promotion peak
+    r->t_submit = now_s();
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (r->bytes > c->budget) return CR_ENOMEM;
+    r->id = c->next_id++;
+    *req_id = r->id;
+    c->queue.push_back(r->id);
+    c->reqs[r->id] = std::move(r);
+    c->admit_locked();
+    return CR_OK;
+}
+
+static int collect(cr_ctx *c, Request *r, int64_t id, double *y, double *xi, cr_report *rep, double *lat) {
+    if (y) std::memcpy(y, r->y.data(), r->y.size() * 8);
+    if (xi) std::memcpy(xi, r->xi.data(), r->xi.size() * 8);
+    if (rep) *rep = r->rep;
+    if (lat) *lat = r->t_done - r->t_submit;
+    const int st = r->status;
+    c->reqs.erase(id);
+    return st;
+}
+
+extern "C" int cr_poll(cr_ctx *c, int64_t id, double *y, double *xi, cr_report *rep, double *latency_s) {
+    if (!c) return CR_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->reqs.find(id);
+    if (it == c->reqs.end()) return CR_ENOTFOUND;
+    if (it->second->state != 2) return CR_EAGAIN;
+    return collect(c, it->second.get(), id, y, xi, rep, latency_s);
+}
+
+extern "C" int cr_wait(cr_ctx *c, int64_t id, double *y, double *xi, cr_report *rep, double *latency_s) {
+    if (!c) return CR_EINVAL;
+    std::unique_lock<std::mutex> lk(c->mu);
+    auto it = c->reqs.find(id);
+    if (it == c->reqs.end()) return CR_ENOTFOUND;
+    Request *r = it->second.get();
+    c->cv_done.wait(lk, [&] { return r->state == 2; });
+    return collect(c, r, id, y, xi, rep, latency_s);
+}
+
+extern "C" int cr_ctx_stats(cr_ctx *c, int64_t *queued, int64_t *running, int64_t *finished, size_t *resident) {
+    if (!c) return CR_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (queued) *queued = (int64_t)c->queue.size();
+    if (running) *running = c->running;
+    if (finished) *finished = c->finished;
+    if (resident) *resident = c->resident;
+    return CR_OK;
+}

@@ -1,0 +1,46 @@
+"""Writes the stored expected values used by the GPU parity tests.
+
+Every value here comes from the FP64 oracle (``oracle/``) run on the seeded workload generators;
+nothing is taken from the GPU path.  Re-run with ``python tests/golden/make_golden.py``.
+"""
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_1608_02227_amd import workloads as W  # noqa: E402
+
+CASES = [
+    # name, workload, seed, N override, tol, check_every
+    ("sqnorm_N200_n2_seed0_tol1e-4", "sqnorm_N200_n2", 0, None, 1e-4, 50),
+    ("lse8_N400_n10_seed1_tol1e-4", "lse8_N2000_n10", 1, 400, 1e-4, 50),
+]
+
+
+def main():
+    for name, wl, seed, N, tol, every in CASES:
+        w = W.WORKLOADS[wl]
+        x, ybar = W.make(wl, seed=seed, N=N)
+        L, s2, pit = oracle.lipschitz(x, w.delta)
+        r = oracle.papg(x, ybar, w.delta, tol, L=L, max_iters=2_000_000, check_every=every)
+        cert = oracle.repair_certificate(x, ybar, w.delta, r["lam"])
+        rep = {k: v for k, v in r["report"].items()}
+        out = {
+            "source": "oracle.papg (FP64 numpy), P-APG of Fig. fig:papg with every pair dualized",
+            "workload": wl, "seed": seed, "N": int(x.shape[0]), "n": int(x.shape[1]), "delta": w.delta,
+            "tol": tol, "check_every": every, "L": L, "sigma2": s2, "power_iters": pit,
+            "iters": r["iters"], "status": r["status"], "report": rep,
+            "cert_gap": cert["cert_gap"], "y_err_bound": cert["y_err_bound"],
+            "y": r["y"].tolist(), "xi": r["xi"].tolist(),
+        }
+        path = os.path.join(HERE, name + ".json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print(name, r["iters"], r["status"], rep["kkt"])
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,91 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared entry point, and its
+host-side argument validation rejects bad input without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["cr_fit", "cr_fit_device", "cr_solver_create", "cr_solver_iterate", "cr_solver_lipschitz",
+                 "cr_solver_report", "cr_op_residual", "cr_op_adjoint", "cr_ctx_create", "cr_submit", "cr_wait"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(cr):
+    lib = cr.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_defaults(cr):
+    assert cr.strerror(0) == "ok"
+    assert "invalid" in cr.strerror(cr.CR_EINVAL)
+    o = cr.CROptions()
+    cr.load().cr_default_options(C.byref(o))
+    assert o.check_every == 50 and o.momentum == 1 and o.precision == 0 and o.power_max_iters == 300
+
+
+@pytest.mark.parametrize("N,n,delta,tol", [(0, 2, 1e-3, 1e-4), (10, 0, 1e-3, 1e-4), (10, 2, 0.0, 1e-4),
+                                            (10, 2, -1.0, 1e-4), (10, 2, 1e-3, 0.0), (10, 2, float("nan"), 1e-4),
+                                            (10, 64, 1e-3, 1e-4)])
+def test_fit_rejects_bad_arguments_on_host(cr, N, n, delta, tol):
+    lib = cr.load()
+    x = np.zeros((max(N, 1), max(n, 1)))
+    yb = np.zeros(max(N, 1))
+    y = np.zeros(max(N, 1))
+    xi = np.zeros((max(N, 1), max(n, 1)))
+    opt = cr.Options().to_c()
+    rc = lib.cr_fit(N, n, cr._ptr(x), cr._ptr(yb), delta, tol, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)
+    assert rc == cr.CR_EINVAL
+
+
+def test_fit_rejects_bad_options_on_host(cr):
+    lib = cr.load()
+    x = np.zeros((4, 2))
+    yb = np.zeros(4)
+    y = np.zeros(4)
+    xi = np.zeros((4, 2))
+    for field, value in [("check_every", 0), ("precision", 7), ("L", -1.0), ("power_max_iters", 0)]:
+        opt = cr.Options().to_c()
+        setattr(opt, field, value)
+        rc = lib.cr_fit(4, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)
+        assert rc == cr.CR_EINVAL, field
+
+
+def test_binding_struct_layout_matches_header(cr, tmp_path):
+    # Compile a probe against cr.h with the host C compiler and compare sizes and offsets.
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields_o = [f for f, _ in cr.CROptions._fields_]
+    fields_r = [f for f, _ in cr.CRReport._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cr.h"', "int main(void){",
+             'printf("%zu %zu\\n", sizeof(cr_options), sizeof(cr_report));']
+    lines += [f'printf("%zu\\n", offsetof(cr_options, {f}));' for f in fields_o]
+    lines += [f'printf("%zu\\n", offsetof(cr_report, {f}));' for f in fields_r]
+    lines += ["return 0;}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == C.sizeof(cr.CROptions)
+    assert int(out[1]) == C.sizeof(cr.CRReport)
+    offs = [int(v) for v in out[2:]]
+    py = [getattr(cr.CROptions, f).offset for f in fields_o] + [getattr(cr.CRReport, f).offset for f in fields_r]
+    assert offs == py
