@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: dual-smoothing (P-APG) convex-regression fits on one MI355X.
+
+One step = one complete fit of the N=8000, n=40 quadratic-form workload to KKT residual 1e-4:
+Lipschitz preprocessing, P-APG iterations (one fused pair pass each), stopping tests every 50
+iterations, FP64 recovery of (y, xi) and the feasible-repair certificate.  Inputs are resident in
+device memory before the timed region; outputs stay on the device.
+
+Prints one JSON line (stdout).  `value` is dual iterations per second over the timed fits
+(whole-fit wall time, preprocessing and stopping tests included); `ms_per_step` is the
+time-to-tolerance of one fit.  Extra fields compare the mixed-precision path with the plain
+FP64 path on the same input, report the roofline of the fused pass, and time the FP64 CPU
+oracle on the host cores on a bounded sample of the same fit.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed_fp32|mixed_bf16|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+WORKLOAD = "quad_N8000_n40"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1608_02227_amd", "csrc", "cr_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_step_traffic_quad_N8000_n40.json")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# Algorithmic HBM bytes per pair and per iteration of the fused pass, by precision mode:
+#   fp64       : read lam^{k-1}, lam^{k-2}, write lam^k, 8 bytes each            -> 24
+#   mixed_fp32 : read H (4), l^{k-1} (4), l^{k-2} (4), write l^k (4)              -> 16
+#   mixed_bf16 : read H (2), l^{k-1} (4), l^{k-2} (4), write l^k (4)              -> 14
+PASS_BYTES = {"fp64": 24, "mixed_fp32": 16, "mixed_bf16": 14}
+PASS_KERNEL = {"fp64": "pass_kernel<double,REP_F64,PASS_STEP,MB=3>",
+               "mixed_fp32": "pass_kernel<float,REP_SPLIT_F32,PASS_STEP,MB=3>",
+               "mixed_bf16": "pass_kernel<float,REP_SPLIT_BF16,PASS_STEP,MB=3>"}
+
+
+def step_kernel_stats(rep: dict, precision: str) -> dict:
+    """Dominant pass kernel of a fit (the phase with the larger total device time)."""
+    low_iters = rep["iters_low"]
+    hi_iters = rep["iters"] - rep["iters_low"]
+    t_low = low_iters * rep["step_ms_low"]
+    t_hi = hi_iters * rep["step_ms_fp64"]
+    if precision != "fp64" and t_low >= t_hi and rep["step_samples_low"] > 0:
+        return {"phase": "low", "ms": rep["step_ms_low"], "bytes_per_pair": PASS_BYTES[precision],
+                "launches": low_iters, "samples": rep["step_samples_low"], "kernel": PASS_KERNEL[precision]}
+    return {"phase": "fp64", "ms": rep["step_ms_fp64"], "bytes_per_pair": PASS_BYTES["fp64"], "launches": hi_iters,
+            "samples": rep["step_samples_fp64"], "kernel": PASS_KERNEL["fp64"]}
+
+
+def traffic_for(kernel: str) -> dict | None:
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return t.get("kernels", {}).get(kernel)
+
+
+def cpu_baseline(x, ybar, delta: float, L: float, iters: int) -> dict:
+    """The FP64 numpy oracle, untuned, on the host cores: `iters` P-APG iterations of the same fit."""
+    import numpy as np
+    import oracle
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads") or 0) for p in threadpool_info()) or None
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=iters, check_every=10 ** 9)
+    dt = time.perf_counter() - t0
+    # the oracle's loop ends with one stopping report; charge it to the sample as well
+    return {"value": iters / dt, "unit": "dual iterations/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{iters} P-APG iterations (plus one stopping report) of the same N={x.shape[0]}, "
+                      f"n={x.shape[1]} fit in the FP64 numpy oracle, L fixed; {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "mixed_bf16", "fp64"])
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison fit")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--max-iters", type=int, default=0,
+                    help="cap the iterations of each fit (short profiling runs of the same kernels)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU row-strip design is described, not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1608_02227_amd import cr
+    from paper_1608_02227_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    cr.load()
+    dev = torch.device("cuda:0")
+    wl = W.WORKLOADS[WORKLOAD]
+    x_h, yb_h = W.make(WORKLOAD, seed=args.seed)
+    x = torch.from_numpy(x_h).to(dev)
+    yb = torch.from_numpy(yb_h).to(dev)
+    torch.cuda.synchronize()
+
+    def one_fit(precision: str):
+        opt = cr.Options(precision=precision, device=0,
+                         stream=torch.cuda.current_stream(dev).cuda_stream)
+        if args.max_iters > 0:
+            opt.max_iters = args.max_iters
+        return cr.fit(x, yb, wl.delta, args.tol, opt)
+
+    for w in range(args.warmup):
+        r = one_fit(args.precision)
+        log(f"warmup {w + 1}/{args.warmup}: {r.report['iters']} iters, kkt {r.report['kkt']:.3e}, "
+            f"{r.report['seconds']:.2f} s")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for k in range(args.steps):
+        results.append(one_fit(args.precision))
+        log(f"step {k + 1}/{args.steps}: {results[-1].report['iters']} iters "
+            f"({results[-1].report['iters_low']} low), kkt {results[-1].report['kkt']:.3e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    reps = [r.report for r in results]
+    iters_total = sum(r["iters"] for r in reps)
+    value = iters_total / elapsed
+    last = reps[-1]
+    ks = step_kernel_stats(last, args.precision)
+    pairs = wl.N * (wl.N - 1)
+    alg_bytes = ks["bytes_per_pair"] * pairs
+    achieved = alg_bytes / (ks["ms"] * 1e-3) / 1e9 if ks["ms"] > 0 else 0.0
+    tr = traffic_for(ks["kernel"])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr["bytes_per_launch"] if tr else None,
+                "kernel": ks["kernel"], "avg_launch_ms": round(ks["ms"], 5), "sampled_launches": int(ks["samples"]),
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "mfma_tflops": round(4.0 * pairs * wl.n / (ks["ms"] * 1e-3) / 1e12, 2) if ks["ms"] > 0 else 0.0}
+
+    extra = {
+        "time_to_tol_s": [round(r["seconds"], 4) for r in reps],
+        "iters": [r["iters"] for r in reps],
+        "iters_low_precision": [r["iters_low"] for r in reps],
+        "kkt_final": last["kkt"],
+        "max_viol_final": last["max_viol"],
+        "preprocess_s": round(last["preprocess_seconds"], 4),
+        "L": last["L"],
+        "cert_gap": last["cert_gap"],
+        "y_err_bound": last["y_err_bound"],
+    }
+
+    if not args.no_compare and args.precision != "fp64":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = one_fit("fp64")
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t1
+        rep64 = r64.report
+        ymix = results[-1].y.cpu().numpy()
+        y64 = r64.y.cpu().numpy()
+        ks64 = step_kernel_stats(rep64, "fp64")
+        extra.update({
+            "fp64_time_to_tol_s": round(dt64, 4),
+            "fp64_iters": rep64["iters"],
+            "fp64_dual_iters_per_s": round(rep64["iters"] / dt64, 1),
+            "fp64_kkt_final": rep64["kkt"],
+            "fp64_step_hbm_gbs": round(24 * pairs / (ks64["ms"] * 1e-3) / 1e9, 1) if ks64["ms"] > 0 else None,
+            "mixed_vs_fp64_speedup": round(dt64 / (elapsed / args.steps), 3),
+            "mixed_vs_fp64_y_maxabs": float(np.max(np.abs(ymix - y64))),
+            "mixed_vs_fp64_y_rel": float(np.max(np.abs(ymix - y64)) / np.max(np.abs(y64))),
+        })
+        log(f"fp64 comparison: {rep64['iters']} iters in {dt64:.2f} s")
+
+    out = {
+        "metric": "dual P-APG iterations/s and time-to-1e-4 KKT, N=8000 n=40 convex-regression fit",
+        "value": round(value, 1),
+        "unit": "dual iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64", "fp64": "f64"}[args.precision],
+        "data": "synthetic (seeded generator, same shapes and distributions as the named workload)",
+        "config": {"workload": f"{WORKLOAD}: x~U[-1,1]^40, f0=x^T Q x with Q=M^T M/40, eps~N(0,0.5^2), "
+                               f"delta=1e-3, KKT tol {args.tol:g}",
+                   "N": wl.N, "n": wl.n, "delta": wl.delta, "tol": args.tol, "precision": args.precision,
+                   "seed": args.seed},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log(f"cpu baseline: {args.cpu_iters} oracle iterations at N={wl.N} ...")
+        out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters)
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -50,9 +50,10 @@ extern "C" {
 /* Arithmetic of the multiplier state and of the pair pass. */
 typedef enum {
     CR_FP64 = 0,        /* lam stored in FP64, FP64 pair pass (FP64 MFMA contractions)          */
-    CR_MIXED_FP32 = 1,  /* lam stored in FP32 with FP32 MFMA contractions until progress stalls,  */
-                        /* then FP64 refinement from the promoted multipliers                     */
-    CR_MIXED_BF16 = 2   /* as CR_MIXED_FP32 but the low-precision phase stores lam in BF16       */
+    CR_MIXED_FP32 = 1,  /* lam = H + l: shared FP32 high part, FP32 low part per iterate; FP32    */
+                        /* MFMA pair pass; FP64 stopping test, adjoint of H and re-basing at each  */
+                        /* test; FP64 refinement (promotion) only if progress stalls               */
+    CR_MIXED_BF16 = 2   /* as CR_MIXED_FP32 with the shared high part H stored in BF16           */
 } cr_precision;
 
 typedef struct {
@@ -67,8 +68,8 @@ typedef struct {
     int32_t certificate;     /* 1: compute the feasible repair and certified gap (default 1) */
     int32_t device;          /* HIP device ordinal; default 0 */
     void *stream;            /* hipStream_t to run on; NULL: the library's own stream */
-    int32_t stall_checks;    /* mixed modes: switch to FP64 after this many checks without a
-                                10% improvement of the KKT residual; default 4 */
+    int32_t stall_checks;    /* mixed modes: switch to FP64 after this many consecutive stopping
+                                tests without a new lowest KKT residual; default 100 */
     int32_t reserved[7];
 } cr_options;
 
@@ -103,7 +104,14 @@ typedef struct {
     double cert_primal;
     double cert_gap;
     double y_err_bound;
-    double reserved[6];
+    /* Device time of the fused pair pass (one launch per iteration), from HIP events recorded
+       on the solver's stream around one launch per stopping-test interval: average ms per
+       launch and number of sampled launches, for the low-precision and the FP64 phase. */
+    double step_ms_low;
+    double step_ms_fp64;
+    double step_samples_low;
+    double step_samples_fp64;
+    double reserved[2];
 } cr_report;
 
 /* Fills *opt with the defaults listed above. */

@@ -65,7 +65,11 @@ class CRReport(C.Structure):
         ("cert_primal", C.c_double),
         ("cert_gap", C.c_double),
         ("y_err_bound", C.c_double),
-        ("reserved", C.c_double * 6),
+        ("step_ms_low", C.c_double),
+        ("step_ms_fp64", C.c_double),
+        ("step_samples_low", C.c_double),
+        ("step_samples_fp64", C.c_double),
+        ("reserved", C.c_double * 2),
     ]
 
     def as_dict(self) -> dict:
@@ -162,7 +166,7 @@ class Options:
     certificate: bool = True
     device: int = 0
     stream: int | None = None
-    stall_checks: int = 4
+    stall_checks: int = 100
 
     def to_c(self) -> CROptions:
         o = CROptions()

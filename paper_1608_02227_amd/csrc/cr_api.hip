@@ -20,7 +20,12 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-size_t lam_bytes(LamType t) { return t == LAM_F64 ? 8 : (t == LAM_F32 ? 4 : 2); }
+LamRep rep_of(int precision) {
+    return precision == CR_FP64 ? REP_F64 : (precision == CR_MIXED_FP32 ? REP_SPLIT_F32 : REP_SPLIT_BF16);
+}
+
+// bytes of the two-iterate multiplier state per (padded) pair
+size_t state_bytes_per_pair(LamRep r) { return r == REP_F64 ? 16 : (r == REP_SPLIT_F32 ? 12 : 10); }
 
 bool all_finite(const double *p, size_t n) {
     for (size_t i = 0; i < n; ++i)
@@ -55,7 +60,7 @@ extern "C" void cr_default_options(cr_options *opt) {
     opt->certificate = 1;
     opt->device = 0;
     opt->stream = nullptr;
-    opt->stall_checks = 4;
+    opt->stall_checks = 100;
 }
 
 extern "C" const char *cr_strerror(int code) {
@@ -110,6 +115,8 @@ void cr_solver::release(void *p) {
 cr_solver::~cr_solver() {
     if (device >= 0) (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
     for (void *p : owned) (void)hipFree(p);
     if (h_scal) (void)hipHostFree(h_scal);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -117,8 +124,7 @@ cr_solver::~cr_solver() {
 
 size_t cr_state_bytes(int64_t N, int64_t n, int precision) {
     Geometry g = make_geometry((int)N, (int)n);
-    const LamType lt = precision == CR_FP64 ? LAM_F64 : (precision == CR_MIXED_FP32 ? LAM_F32 : LAM_BF16);
-    size_t b = 2 * (size_t)g.Nr * g.ld * lam_bytes(lt);
+    size_t b = (size_t)g.Nr * g.ld * state_bytes_per_pair(rep_of(precision));
     b += (size_t)g.chunks * g.Nr * g.NP * 8 + (size_t)g.strips * g.ld * 12;
     b += (size_t)g.Nr * g.NP * 8 * 6 + (size_t)g.Nr * 8 * 16;
     return b;
@@ -165,7 +171,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     s->delta = delta;
     s->g = make_geometry((int)N, (int)n);
     s->precision = opt.precision;
-    s->lt = opt.precision == CR_FP64 ? LAM_F64 : (opt.precision == CR_MIXED_FP32 ? LAM_F32 : LAM_BF16);
+    s->rep = rep_of(opt.precision);
     s->fp32pass = opt.precision != CR_FP64;
     double ymin = hy[0], ymax = hy[0];
     for (double v : hy) { ymin = std::min(ymin, v); ymax = std::max(ymax, v); }
@@ -181,13 +187,20 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     }
     if (hipHostMalloc((void **)&s->h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return bail(CR_ENOMEM);
+    if (hipEventCreate(&s->ev_a) != hipSuccess || hipEventCreate(&s->ev_b) != hipSuccess) return bail(CR_EDEVICE);
 
     const Geometry &g = s->g;
     const size_t nr = g.Nr, np = g.NP, rows_np = nr * np;
-    const size_t lamsz = nr * g.ld * lam_bytes(s->lt);
+    const size_t pairs_p = nr * g.ld;
+    const size_t lamsz = pairs_p * (s->rep == REP_F64 ? 8 : 4);
 #define CR_ALLOC(ptr, bytes) do { int r_ = s->alloc((void **)&(ptr), (bytes)); if (r_) return bail(r_); } while (0)
     CR_ALLOC(s->lam[0], lamsz);
     CR_ALLOC(s->lam[1], lamsz);
+    if (s->rep != REP_F64) {
+        CR_ALLOC(s->lam_hi, pairs_p * (s->rep == REP_SPLIT_F32 ? 4 : 2));
+        CR_ALLOC(s->ubase, nr * 8);
+        CR_ALLOC(s->wbase, rows_np * 8);
+    }
     CR_ALLOC(s->xhat64, rows_np * 8);
     CR_ALLOC(s->ybar64, nr * 8);
     CR_ALLOC(s->y64, nr * 8);
@@ -245,13 +258,18 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         for (double v : hl)
             if (!std::isfinite(v) || v < 0.0) { H(hipStreamSynchronize(s->stream)); return bail(CR_EINVAL); }
         H(hipMemcpyAsync(dl, hl.data(), hl.size() * 8, hipMemcpyHostToDevice, s->stream));
-        H(launch_pack_lambda(g, dl, s->lam[0], s->lt, s->stream));
-        H(launch_pack_lambda(g, dl, s->lam[1], s->lt, s->stream));
+        H(launch_pack_lambda(g, dl, s->rep, s->rep == REP_F64 ? s->lam[0] : s->lam_hi, (float *)s->lam[0], s->stream));
+        H(hipMemcpyAsync(s->lam[1], s->lam[0], lamsz, hipMemcpyDeviceToDevice, s->stream));
         H(hipStreamSynchronize(s->stream));
         s->release(dl);
     } else {
         H(hipMemsetAsync(s->lam[0], 0, lamsz, s->stream));
         H(hipMemsetAsync(s->lam[1], 0, lamsz, s->stream));
+        if (s->lam_hi) H(hipMemsetAsync(s->lam_hi, 0, pairs_p * (s->rep == REP_SPLIT_F32 ? 4 : 2), s->stream));
+    }
+    if (s->ubase) {
+        H(hipMemsetAsync(s->ubase, 0, nr * 8, s->stream));
+        H(hipMemsetAsync(s->wbase, 0, rows_np * 8, s->stream));
     }
     H(hipMemsetAsync(s->part_acc, 0, (size_t)g.chunks * rows_np * 8, s->stream));
     H(hipMemsetAsync(s->part_col, 0, (size_t)g.strips * g.ld * 8, s->stream));
@@ -276,15 +294,16 @@ extern "C" int cr_solver_destroy(cr_solver *s) {
 
 // ---- passes ---------------------------------------------------------------------------------
 
-// Adjoint of stored multipliers `lam` (storage lt) in FP64 -> primal arrays (y, xi, dmy).
-int cr_solver::adjoint_to(const void *lam_p, LamType lt_p, double *y, double *xi, double *dmy, bool with_rowred,
-                          float *y32_, float *xi32_, float *dmy32_) {
+// FP64 adjoint of the stored iterate `idx` -> primal arrays (y, xi, dmy) and optional copies.
+int cr_solver::adjoint_to(int idx, double *y, double *xi, double *dmy, bool with_rowred, float *y32_, float *xi32_,
+                          float *dmy32_) {
     PassArgs a{};
-    a.lam_a = lam_p;
+    a.lam_h = lam_hi;
+    a.lam_a = lam[idx];
     a.xhat = xhat64;
     a.part_acc = part_acc;
     a.part_col = part_col;
-    CR_HIP(launch_pass(g, PASS_ADJ, false, lt_p, a, stream));
+    CR_HIP(launch_pass(g, PASS_ADJ, false, rep, a, stream));
     FinalizeArgs f{};
     f.part_acc = part_acc;
     f.part_col = part_col;
@@ -299,22 +318,44 @@ int cr_solver::adjoint_to(const void *lam_p, LamType lt_p, double *y, double *xi
     return CR_OK;
 }
 
+// Split representations: fold lam^k's low part into the shared high part (H <- round(H + l_k)),
+// re-express both low parts against it and cache the FP64 adjoint C^T H for the next steps.
+int cr_solver::rebase() {
+    if (rep == REP_F64) return CR_OK;
+    PassArgs a{};
+    a.lam_h = lam_hi;
+    a.lam_a = lam[cur];
+    a.lam_b = lam[1 - cur];
+    a.xhat = xhat64;
+    a.part_acc = part_acc;
+    a.part_col = part_col;
+    CR_HIP(launch_pass(g, PASS_REBASE, false, rep, a, stream));
+    FinalizeArgs f{};
+    f.part_acc = part_acc;
+    f.part_col = part_col;
+    f.xf = xhat64;
+    f.ybar = ybar64;
+    f.y = ubase; f.xi = wbase; f.dmy = dmyr;
+    f.inv_delta = 1.0;
+    f.power = 1;
+    CR_HIP(launch_finalize(g, false, f, stream));
+    return CR_OK;
+}
+
 // eta^{k+1} for the next step from the current multipliers (used before the first iteration
-// and after a change of precision or of the pass arrays).
+// and after a change of representation or of the pass arrays).
 int cr_solver::prime() {
-    // lam~^{k+1} = lam^k + beta_k (lam^k - lam^{k-1}); at k = 0 both buffers hold lam^0.  After a
-    // power iteration (k = 0) or a promotion, beta is applied by running the adjoint of lam~
-    // through a STEP-free path: the extrapolated point is formed explicitly in a scratch pass.
+    int rc = rebase();
+    if (rc) return rc;
+    // lam~^{k+1} = lam^k + beta_k (lam^k - lam^{k-1}) is linear in the stored iterates, so its
+    // adjoint is (1 + beta) C^T lam^k - beta C^T lam^{k-1}; at k = 0 (or beta = 0) only lam^k counts.
     if (k == 0 || beta_last == 0.0) {
-        int rc = adjoint_to(lam[cur], lt, y64, xi64, dmy64, false, y32, xi32, dmy32);
+        rc = adjoint_to(cur, y64, xi64, dmy64, false, y32, xi32, dmy32);
         if (rc) return rc;
     } else {
-        // general case: form lam~ in the other buffer's storage is not allowed (it holds
-        // lam^{k-1}); instead accumulate lam^k and lam^{k-1} adjoints and combine linearly:
-        // C^T lam~ = (1 + beta) C^T lam^k - beta C^T lam^{k-1}.
-        int rc = adjoint_to(lam[cur], lt, yc, xic, dmyc, false, nullptr, nullptr, nullptr);
+        rc = adjoint_to(cur, yc, xic, dmyc, false, nullptr, nullptr, nullptr);
         if (rc) return rc;
-        rc = adjoint_to(lam[1 - cur], lt, yr, xir, dmyr, false, nullptr, nullptr, nullptr);
+        rc = adjoint_to(1 - cur, yr, xir, dmyr, false, nullptr, nullptr, nullptr);
         if (rc) return rc;
         CR_HIP(launch_combine(g, yc, xic, yr, xir, ybar64, xhat64, beta_last, y64, xi64, dmy64, y32, xi32, dmy32,
                               stream));
@@ -331,6 +372,7 @@ int cr_solver::step_once() {
     const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
     const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
     PassArgs a{};
+    a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[1 - cur];
     a.beta_prev = opt.momentum ? beta_last : 0.0;
@@ -343,7 +385,14 @@ int cr_solver::step_once() {
     } else {
         a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
     }
-    CR_HIP(launch_pass(g, PASS_STEP, fp32pass, lt, a, stream));
+    const bool timed = !ev_pending;
+    if (timed) CR_HIP(hipEventRecord(ev_a, stream));
+    CR_HIP(launch_pass(g, PASS_STEP, fp32pass, rep, a, stream));
+    if (timed) {
+        CR_HIP(hipEventRecord(ev_b, stream));
+        ev_pending = true;
+        ev_pending_low = fp32pass;
+    }
     FinalizeArgs f{};
     f.part_acc = part_acc;
     f.part_col = part_col;
@@ -353,6 +402,8 @@ int cr_solver::step_once() {
     f.y32 = fp32pass ? y32 : nullptr;
     f.xi32 = fp32pass ? xi32 : nullptr;
     f.dmy32 = fp32pass ? dmy32 : nullptr;
+    f.ubase = ubase;
+    f.wbase = wbase;
     f.inv_delta = 1.0 / delta;
     CR_HIP(launch_finalize(g, fp32pass, f, stream));
     cur = 1 - cur;
@@ -361,6 +412,18 @@ int cr_solver::step_once() {
     ++k;
     if (fp32pass) ++k_low;
     return CR_OK;
+}
+
+// Folds the last sampled launch into the averages (call after the stream has synchronized).
+void cr_solver::collect_timing() {
+    if (!ev_pending) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev_a, ev_b) == hipSuccess) {
+        const int q = ev_pending_low ? 0 : 1;
+        step_ms_sum[q] += ms;
+        step_n[q] += 1.0;
+    }
+    ev_pending = false;
 }
 
 int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
@@ -373,7 +436,7 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
         PassArgs a{};
         a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
         a.part_acc = part_acc; a.part_col = part_col; a.part_red = part_red;
-        CR_HIP(launch_pass(g, PASS_POWER, false, LAM_F64, a, stream));
+        CR_HIP(launch_pass(g, PASS_POWER, false, REP_F64, a, stream));
         FinalizeArgs f{};
         f.part_acc = part_acc; f.part_col = part_col; f.xf = xhat64; f.ybar = ybar64;
         f.y = y64; f.xi = xi64; f.dmy = dmy64; f.rowred = rowred; f.inv_delta = 1.0; f.power = 1;
@@ -404,14 +467,17 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
 }
 
 // FP64 stopping test at lam^k; fills rep (without timing fields).  Leaves eta(lam^k) in yc/xic.
-int cr_solver::check(cr_report *rep, bool certificate) {
-    int rc = adjoint_to(lam[cur], lt, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
+int cr_solver::check(cr_report *rep_out, bool certificate) {
+    int rc = rebase();
+    if (rc) return rc;
+    rc = adjoint_to(cur, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
     if (rc) return rc;
     PassArgs a{};
+    a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.xhat = xhat64; a.xi = xic; a.yv = yc; a.dmy = dmyc;
     a.part_red = part_red;
-    CR_HIP(launch_pass(g, PASS_KKT, false, lt, a, stream));
+    CR_HIP(launch_pass(g, PASS_KKT, false, this->rep, a, stream));
     CR_HIP(launch_reduce(part_red, g.grid(), kRed, 2, 4, scal, stream));
     CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 4, stream));
     int nsc = 6;
@@ -419,48 +485,53 @@ int cr_solver::check(cr_report *rep, bool certificate) {
         PassArgs r{};
         r.xhat = xhat64; r.xi = xic; r.yv = yc; r.dmy = dmyc;
         r.part_min = part_min; r.part_arg = part_arg;
-        CR_HIP(launch_pass(g, PASS_REPAIR, false, LAM_F64, r, stream));
+        CR_HIP(launch_pass(g, PASS_REPAIR, false, REP_F64, r, stream));
         CR_HIP(launch_repair_finish(g, part_min, part_arg, yc, xic, ybar64, yr, xir, rowred, stream));
         CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 6, stream));
         nsc = 8;
     }
     CR_HIP(hipMemcpyAsync(h_scal, scal, nsc * sizeof(double), hipMemcpyDeviceToHost, stream));
     CR_HIP(hipStreamSynchronize(stream));
+    collect_timing();
     const double pairs = (double)g.N * (double)g.N - (double)g.N;
-    std::memset(rep, 0, sizeof(*rep));
-    rep->precision = precision;
-    rep->iters = k;
-    rep->iters_low = k_low;
-    rep->L = L;
-    rep->sigma2 = sigma2;
-    rep->power_iters = power_iters;
-    rep->preprocess_seconds = preprocess_s;
-    rep->scale = scale;
-    rep->nat_res_max = h_scal[0] / scale;
-    rep->max_viol = h_scal[1] / scale;
-    rep->infeas_rms = pairs > 0 ? std::sqrt(h_scal[2] / pairs) : 0.0;
-    rep->comp_sum = h_scal[3];
-    rep->dual_gap_paper = pairs > 0 ? std::fabs(h_scal[3]) / pairs : 0.0;
-    rep->primal_obj = 0.5 * h_scal[4] + 0.5 * delta * h_scal[5];
-    rep->dual_obj = rep->primal_obj - rep->comp_sum;
+    std::memset(rep_out, 0, sizeof(*rep_out));
+    rep_out->precision = precision;
+    rep_out->iters = k;
+    rep_out->iters_low = k_low;
+    rep_out->L = L;
+    rep_out->sigma2 = sigma2;
+    rep_out->power_iters = power_iters;
+    rep_out->preprocess_seconds = preprocess_s;
+    rep_out->scale = scale;
+    rep_out->nat_res_max = h_scal[0] / scale;
+    rep_out->max_viol = h_scal[1] / scale;
+    rep_out->infeas_rms = pairs > 0 ? std::sqrt(h_scal[2] / pairs) : 0.0;
+    rep_out->comp_sum = h_scal[3];
+    rep_out->dual_gap_paper = pairs > 0 ? std::fabs(h_scal[3]) / pairs : 0.0;
+    rep_out->primal_obj = 0.5 * h_scal[4] + 0.5 * delta * h_scal[5];
+    rep_out->dual_obj = rep_out->primal_obj - rep_out->comp_sum;
     // The returned (y, xi) are the FP64 closed form of lam^k, so stationarity holds to rounding.
-    rep->stat_y = 0.0;
-    rep->stat_xi = 0.0;
-    rep->kkt = std::max(rep->nat_res_max, std::max(rep->stat_y, rep->stat_xi));
+    rep_out->stat_y = 0.0;
+    rep_out->stat_xi = 0.0;
+    rep_out->kkt = std::max(rep_out->nat_res_max, std::max(rep_out->stat_y, rep_out->stat_xi));
     if (certificate) {
-        rep->cert_primal = 0.5 * h_scal[6] + 0.5 * delta * h_scal[7];
-        rep->cert_gap = rep->cert_primal - rep->dual_obj;
-        rep->y_err_bound = std::sqrt(std::max(0.0, 2.0 * rep->cert_gap));
+        rep_out->cert_primal = 0.5 * h_scal[6] + 0.5 * delta * h_scal[7];
+        rep_out->cert_gap = rep_out->cert_primal - rep_out->dual_obj;
+        rep_out->y_err_bound = std::sqrt(std::max(0.0, 2.0 * rep_out->cert_gap));
     }
+    rep_out->step_samples_low = step_n[0];
+    rep_out->step_samples_fp64 = step_n[1];
+    rep_out->step_ms_low = step_n[0] > 0 ? step_ms_sum[0] / step_n[0] : 0.0;
+    rep_out->step_ms_fp64 = step_n[1] > 0 ? step_ms_sum[1] / step_n[1] : 0.0;
     bool finite = true;
     for (int q = 0; q < nsc; ++q) finite = finite && std::isfinite(h_scal[q]);
-    rep->status = finite ? CR_OK : CR_ENUMERIC;
+    rep_out->status = finite ? CR_OK : CR_ENUMERIC;
     checked_k = k;
     return finite ? CR_OK : CR_ENUMERIC;
 }
 
 int cr_solver::promote() {
-    if (lt == LAM_F64 && !fp32pass) return CR_OK;
+    if (rep == REP_F64) return CR_OK;
     CR_HIP(hipSetDevice(device));
     const size_t bytes = (size_t)g.Nr * g.ld * 8;
     void *n0 = nullptr, *n1 = nullptr;
@@ -468,14 +539,20 @@ int cr_solver::promote() {
     if (rc) return rc;
     rc = alloc(&n1, bytes);
     if (rc) { release(n0); return rc; }
-    CR_HIP(launch_convert(g, lam[0], lt, n0, LAM_F64, stream));
-    CR_HIP(launch_convert(g, lam[1], lt, n1, LAM_F64, stream));
+    CR_HIP(launch_merge(g, rep, lam_hi, (const float *)lam[0], (double *)n0, stream));
+    CR_HIP(launch_merge(g, rep, lam_hi, (const float *)lam[1], (double *)n1, stream));
     CR_HIP(hipStreamSynchronize(stream));
     release(lam[0]);
     release(lam[1]);
+    release(lam_hi);
+    release(ubase);
+    release(wbase);
     lam[0] = n0;
     lam[1] = n1;
-    lt = LAM_F64;
+    lam_hi = nullptr;
+    ubase = nullptr;
+    wbase = nullptr;
+    rep = REP_F64;
     fp32pass = false;
     primed = false;   // eta^{k+1} is recomputed in FP64 from the promoted multipliers
     return CR_OK;
@@ -496,17 +573,24 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
     int since_best = 0;
     int checks = 0;
     const int64_t kmax = opt.max_iters;
+    const bool trace = getenv("CR_TRACE") != nullptr;
     // iteration 0 check: lam^0 may already be optimal (e.g. convex data)
     for (;;) {
         int rc = check(&rep, false);
         ++checks;
+        if (trace)
+            fprintf(stderr, "cr trace: k=%lld kkt=%.4e viol=%.4e infeas=%.4e dual=%.12e low=%d t=%.3f\n",
+                    (long long)k, rep.kkt, rep.max_viol, rep.infeas_rms, rep.dual_obj, fp32pass ? 1 : 0,
+                    now_s() - t0);
         if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
         if (rc) return rc;
         if (rep.kkt <= tol) { status = CR_OK; break; }
         if (k >= kmax) break;
         if (opt.time_budget_s > 0.0 && now_s() - t0 > opt.time_budget_s) break;
         if (fp32pass) {
-            if (rep.kkt < 0.9 * best) { best = rep.kkt; since_best = 0; }
+            // safety net only: the split representation tracks FP64 to ~1e-9 in y, so a switch
+            // happens only after `stall_checks` tests without any new lowest residual
+            if (rep.kkt < best) { best = rep.kkt; since_best = 0; }
             else if (++since_best >= opt.stall_checks) {
                 rc = promote();
                 if (rc) return rc;
@@ -559,6 +643,7 @@ extern "C" int cr_solver_iterate(cr_solver *s, int64_t iters) {
         if (rc) return rc;
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess) return CR_EDEVICE;
+    s->collect_timing();
     return CR_OK;
 }
 
@@ -581,7 +666,8 @@ extern "C" int cr_solver_get_lambda(cr_solver *s, double *lambda) {
     const size_t bytes = (size_t)s->g.N * s->g.N * 8;
     int rc = s->alloc((void **)&d, bytes);
     if (rc) return rc;
-    CR_HIP(launch_unpack_lambda(s->g, s->lam[s->cur], s->lt, d, s->stream));
+    CR_HIP(launch_unpack_lambda(s->g, s->rep, s->rep == REP_F64 ? s->lam[s->cur] : s->lam_hi,
+                                (const float *)s->lam[s->cur], d, s->stream));
     CR_HIP(hipMemcpyAsync(lambda, d, bytes, hipMemcpyDeviceToHost, s->stream));
     CR_HIP(hipStreamSynchronize(s->stream));
     s->release(d);
@@ -615,7 +701,7 @@ static int primal_out(cr_solver *s, const double *ysrc, const double *xisrc, dou
 extern "C" int cr_solver_get_primal(cr_solver *s, double *y, double *xi) {
     if (!s || !y || !xi) return CR_EINVAL;
     CR_HIP(hipSetDevice(s->device));
-    int rc = s->adjoint_to(s->lam[s->cur], s->lt, s->yc, s->xic, s->dmyc, false, nullptr, nullptr, nullptr);
+    int rc = s->adjoint_to(s->cur, s->yc, s->xic, s->dmyc, false, nullptr, nullptr, nullptr);
     if (rc) return rc;
     return primal_out(s, s->yc, s->xic, y, xi, false);
 }
@@ -677,7 +763,8 @@ static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, d
     if (rc) { delete s; return rc; }
     if (lambda) {
         if (dev) {
-            if (launch_unpack_lambda(s->g, s->lam[s->cur], s->lt, lambda, s->stream) != hipSuccess ||
+            if (launch_unpack_lambda(s->g, s->rep, s->rep == REP_F64 ? s->lam[s->cur] : s->lam_hi,
+                                     (const float *)s->lam[s->cur], lambda, s->stream) != hipSuccess ||
                 hipStreamSynchronize(s->stream) != hipSuccess) { delete s; return CR_EDEVICE; }
         } else {
             rc = cr_solver_get_lambda(s, lambda);
@@ -723,8 +810,8 @@ extern "C" int cr_op_residual(int64_t N, int64_t n, const double *x, const doubl
         PassArgs a{};
         a.lam_b = s->lam[0];
         a.xhat = s->xhat64; a.xi = s->xic; a.yv = s->yc; a.dmy = s->dmyc;
-        if (launch_pass(s->g, PASS_RESID, false, LAM_F64, a, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
-        if (launch_unpack_lambda(s->g, s->lam[0], LAM_F64, s_out, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (launch_pass(s->g, PASS_RESID, false, REP_F64, a, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (launch_unpack_lambda(s->g, REP_F64, s->lam[0], nullptr, s_out, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
         if (hipStreamSynchronize(s->stream) != hipSuccess) rc = CR_EDEVICE;
     } while (0);
     delete s;
@@ -746,13 +833,13 @@ extern "C" int cr_op_adjoint(int64_t N, int64_t n, const double *x, const double
     if (rc) return rc;
     rc = CR_OK;
     do {
-        if (launch_pack_lambda(s->g, lam, s->lam[0], LAM_F64, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (launch_pack_lambda(s->g, lam, REP_F64, s->lam[0], nullptr, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
         PassArgs a{};
         a.lam_a = s->lam[0];
         a.xhat = s->xhat64;
         a.part_acc = s->part_acc;
         a.part_col = s->part_col;
-        if (launch_pass(s->g, PASS_ADJ, false, LAM_F64, a, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
+        if (launch_pass(s->g, PASS_ADJ, false, REP_F64, a, s->stream) != hipSuccess) { rc = CR_EDEVICE; break; }
         FinalizeArgs f{};
         f.part_acc = s->part_acc; f.part_col = s->part_col; f.xf = s->xhat64; f.ybar = s->ybar64;
         f.y = s->yc; f.xi = s->xic; f.dmy = s->dmyc; f.inv_delta = 1.0; f.power = 1;

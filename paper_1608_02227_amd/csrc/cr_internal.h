@@ -15,11 +15,13 @@ struct cr_solver {
     double delta = 1.0;
     double scale = 1.0;          // S_y = max(1, max ybar - min ybar)
     int precision = CR_FP64;     // requested mode
-    cr::LamType lt = cr::LAM_F64;  // current multiplier storage
+    cr::LamRep rep = cr::REP_F64;  // current multiplier representation
     bool fp32pass = false;       // current pass arithmetic is FP32
 
     // device buffers (padded as described by Geometry)
-    void *lam[2] = {nullptr, nullptr};
+    void *lam[2] = {nullptr, nullptr};   // per iterate: FP64 matrix, or FP32 low part (split)
+    void *lam_hi = nullptr;              // split: shared high part
+    double *ubase = nullptr, *wbase = nullptr;   // split: FP64 C^T H
     double *xhat64 = nullptr, *ybar64 = nullptr;
     double *y64 = nullptr, *xi64 = nullptr, *dmy64 = nullptr;      // eta^{k+1} for the next step
     float *xhat32 = nullptr, *y32 = nullptr, *xi32 = nullptr, *dmy32 = nullptr;
@@ -43,11 +45,19 @@ struct cr_solver {
     bool primed = false;
     cr_report last_report{};
 
+    // sampled device time of the fused pass (events on `stream`)
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    bool ev_pending = false, ev_pending_low = false;
+    double step_ms_sum[2] = {0.0, 0.0};   // [0] low precision, [1] FP64
+    double step_n[2] = {0.0, 0.0};
+    void collect_timing();
+
     ~cr_solver();
     int alloc(void **p, size_t bytes);
     void release(void *p);
-    int adjoint_to(const void *lam_p, cr::LamType lt_p, double *y, double *xi, double *dmy, bool with_rowred,
-                   float *y32_, float *xi32_, float *dmy32_);
+    int adjoint_to(int idx, double *y, double *xi, double *dmy, bool with_rowred, float *y32_, float *xi32_,
+                   float *dmy32_);
+    int rebase();
     int prime();
     int step_once();
     int lipschitz(double *L, double *s2, int32_t *it);

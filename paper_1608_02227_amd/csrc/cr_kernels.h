@@ -6,21 +6,33 @@
 
 namespace cr {
 
-// Storage type of the N x N multiplier buffers.
-enum LamType : int { LAM_F64 = 0, LAM_F32 = 1, LAM_BF16 = 2 };
+// Representation of the N x N multiplier state.
+//   REP_F64        : one FP64 matrix per iterate.
+//   REP_SPLIT_F32  : lam = H + l with a high part H (FP32) shared by the two stored iterates and
+//                    one FP32 low part per iterate (16 bytes per pair per iteration instead of 24).
+//   REP_SPLIT_BF16 : the same with H in BF16 (14 bytes per pair per iteration).
+// The split forms keep FP64-level resolution of the small per-iteration updates (steps of
+// s/L can be 1e-11 against multipliers of 1e-2), which a plain FP32 matrix rounds away.
+enum LamRep : int { REP_F64 = 0, REP_SPLIT_F32 = 1, REP_SPLIT_BF16 = 2 };
 
-// What one sweep over the pairs computes (all modes form the residual tile s = C eta except ADJ).
+// What one sweep over the pairs computes (all modes form the residual tile s = C eta except
+// ADJ and REBASE).
 enum PassMode : int {
     PASS_STEP = 0,   // Steps 2-4 fused with the adjoint of the next extrapolated point
     PASS_ADJ = 1,    // adjoint C^T lam of a stored multiplier matrix
     PASS_KKT = 2,    // stopping-test reductions at a stored multiplier matrix
     PASS_POWER = 3,  // z = C v and C^T z (power iteration), plus ||z||^2
     PASS_REPAIR = 4, // column minima of s and their arg-min rows (max-affine repair)
-    PASS_RESID = 5   // writes s = C eta (FP64, zero diagonal and padding) into lam_b
+    PASS_RESID = 5,  // writes s = C eta (FP64, zero diagonal and padding) into lam_b
+    PASS_REBASE = 6  // split forms: H <- round(H + l_k), both low parts re-expressed against the
+                     // new H, and the FP64 adjoint of the new H (cached for the next steps)
 };
 
 // Tiling shared by host and device code.
-constexpr int kWaves = 4;                // waves per workgroup
+#ifndef CR_WAVES
+#define CR_WAVES 4
+#endif
+constexpr int kWaves = CR_WAVES;         // waves per workgroup
 constexpr int kRows = 16 * kWaves;       // rows i per workgroup (one 16-row MFMA block per wave)
 constexpr int kSuper = 64;               // columns j staged in LDS per step
 constexpr int kMaxMB = 4;                // feature blocks of 16: n + 1 <= 64
@@ -43,9 +55,12 @@ struct Geometry {
 Geometry make_geometry(int N, int n);
 
 // One sweep over all pairs.  T is the arithmetic type of the contraction and epilogue; the
-// multiplier buffers use storage `lt`.  Pointer roles (all device, padded as in Geometry):
-//   lam_a   : lam^{k-1} (STEP) or the multipliers to read (ADJ, KKT); unused by POWER/REPAIR
-//   lam_b   : lam^{k-2} in, lam^k out (STEP only)
+// multipliers use representation `rep`.  Pointer roles (all device, padded as in Geometry):
+//   lam_h   : split forms: the shared high part H (FP32 or BF16), Nr x ld
+//   lam_a   : REP_F64: lam^{k-1} (STEP) or the multipliers to read (ADJ, KKT);
+//             split: the FP32 low part of lam^{k-1} (STEP), of lam (ADJ, KKT), of lam^k (REBASE)
+//   lam_b   : REP_F64: lam^{k-2} in, lam^k out (STEP); s out (RESID);
+//             split: low part of lam^{k-2} in, of lam^k out (STEP); of lam^{k-1} (REBASE)
 //   xhat    : Nr x NP locations of type T; column n is 1 for real rows, padding is 0
 //   xi      : Nr x NP subgradients (or the power vector's xi part), type T, zero padded
 //   yv      : Nr fitted values (or the power vector's y part), type T
@@ -56,6 +71,7 @@ Geometry make_geometry(int N, int n);
 //             POWER: sum z^2)
 //   part_min / part_arg: strips x ld column minima and arg-min rows (REPAIR)
 struct PassArgs {
+    void *lam_h;
     const void *lam_a;
     void *lam_b;
     const void *xhat;
@@ -72,7 +88,7 @@ struct PassArgs {
     double inv_L;       // 1 / L
 };
 
-hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamType lt,
+hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,
                        const PassArgs &a, hipStream_t st);
 
 // Finalize: turn the partial sums of one sweep into the primal point.
@@ -81,11 +97,15 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamType lt,
 // Inputs: the partials of type T (fp32 flag), xf (Nr x NP, FP64 locations matching the pass),
 // ybar (Nr).  Outputs: FP64 y, xi, dmy (Nr, Nr x NP, Nr); optional float copies y32/xi32/dmy32
 // (may be null); rowred (Nr x 2: (y - ybar)^2 or y^2, and ||xi||^2), may be null.
+//   ubase/wbase (optional, FP64 Nr / Nr x NP): adjoint of a cached high part, added to the
+//   partial sums before the primal formula (split representations).
 struct FinalizeArgs {
     const void *part_acc;
     const void *part_col;
     const double *xf;
     const double *ybar;
+    const double *ubase;
+    const double *wbase;
     double *y, *xi, *dmy;
     float *y32, *xi32, *dmy32;
     double *rowred;
@@ -103,16 +123,17 @@ hipError_t launch_reduce(const double *part, int blocks, int stride, int nmax, i
 hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dmy,
                             const double *sq, hipStream_t st);
 
-// Converts between multiplier storages; src and dst are Nr x ld.
-hipError_t launch_convert(const Geometry &g, const void *src, LamType st_, void *dst, LamType dt,
-                          hipStream_t st);
+// FP64 multipliers (Nr x ld) from a split representation: dst = H + lo.
+hipError_t launch_merge(const Geometry &g, LamRep rep, const void *hi, const float *lo, double *dst,
+                        hipStream_t st);
 
-// Copies a dense N x N FP64 matrix (row stride N) into / out of a padded buffer of storage lt,
-// zeroing the diagonal and the padding on the way in.
-hipError_t launch_pack_lambda(const Geometry &g, const double *dense, void *dst, LamType lt,
+// Dense N x N FP64 (row stride N) into / out of the padded representation (diagonal and padding
+// zeroed on the way in).  REP_F64: `main` is the FP64 matrix and `lo` is unused; split forms:
+// `main` is H and `lo` the low part of the iterate (split as H = round(lam), lo = lam - H).
+hipError_t launch_pack_lambda(const Geometry &g, const double *dense, LamRep rep, void *main, float *lo,
                               hipStream_t st);
-hipError_t launch_unpack_lambda(const Geometry &g, const void *src, LamType lt, double *dense,
-                                hipStream_t st);
+hipError_t launch_unpack_lambda(const Geometry &g, LamRep rep, const void *main, const float *lo,
+                                double *dense, hipStream_t st);
 
 // Builds xhat (FP64 x - mu, ones in column n, zero padding) and optionally its float copy
 // from dense N x n locations, and pads ybar (may be null).  mu may be null (no shift).

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 namespace cr {
 
@@ -39,80 +40,97 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
 }
 
 // ---- multiplier storage -------------------------------------------------------------------
-struct bf16_t { uint16_t bits; };
-
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-// Round-to-nearest-even; values here are finite and non-negative.
+// Round-to-nearest-even of a finite float to BF16.
 __device__ __forceinline__ uint16_t float_to_bf16(float f) {
     uint32_t u = __float_as_uint(f);
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
 
-template <typename LT, typename T> struct Store;
-template <typename T> struct Store<double, T> {
-    __device__ __forceinline__ static T quant(T v) { return v; }
-    __device__ __forceinline__ static void load4(const double *p, T v[4]) {
-        const d4 q = *reinterpret_cast<const d4 *>(p);
-        v[0] = (T)q[0]; v[1] = (T)q[1]; v[2] = (T)q[2]; v[3] = (T)q[3];
-    }
-    __device__ __forceinline__ static void store4(double *p, const T v[4]) {
-        d4 q = {(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
-        *reinterpret_cast<d4 *>(p) = q;
-    }
+__device__ __forceinline__ d4 ld_d4(const double *p) { return *reinterpret_cast<const d4 *>(p); }
+__device__ __forceinline__ f4 ld_f4(const float *p) { return *reinterpret_cast<const f4 *>(p); }
+__device__ __forceinline__ uint2 ld_u2(const uint16_t *p) { return *reinterpret_cast<const uint2 *>(p); }
+
+// Raw registers of one lane's pairs of a tile (CPL consecutive columns), per representation.
+// REP_F64 lanes hold 4 columns (32 bytes per matrix); the split forms hold 8 columns so that every
+// row segment a lane group reads is a whole 128-byte line in each array.
+template <int REP> struct Raw;
+template <> struct Raw<REP_F64> {
+    static constexpr int CPL = 4;
+    d4 p, q;
 };
-template <typename T> struct Store<float, T> {
-    __device__ __forceinline__ static T quant(T v) { return (T)(float)v; }
-    __device__ __forceinline__ static void load4(const float *p, T v[4]) {
-        const f4 q = *reinterpret_cast<const f4 *>(p);
-        v[0] = (T)q[0]; v[1] = (T)q[1]; v[2] = (T)q[2]; v[3] = (T)q[3];
-    }
-    __device__ __forceinline__ static void store4(float *p, const T v[4]) {
-        f4 q = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-        *reinterpret_cast<f4 *>(p) = q;
-    }
+template <> struct Raw<REP_SPLIT_F32> {
+    static constexpr int CPL = 8;
+    f4 h[2], a[2], b[2];
 };
-template <typename T> struct Store<bf16_t, T> {
-    __device__ __forceinline__ static T quant(T v) { return (T)bf16_to_float(float_to_bf16((float)v)); }
-    __device__ __forceinline__ static void load4(const bf16_t *p, T v[4]) {
-        const uint2 q = *reinterpret_cast<const uint2 *>(p);
-        v[0] = (T)bf16_to_float((uint16_t)(q.x & 0xFFFFu));
-        v[1] = (T)bf16_to_float((uint16_t)(q.x >> 16));
-        v[2] = (T)bf16_to_float((uint16_t)(q.y & 0xFFFFu));
-        v[3] = (T)bf16_to_float((uint16_t)(q.y >> 16));
-    }
-    __device__ __forceinline__ static void store4(bf16_t *p, const T v[4]) {
-        uint2 q;
-        q.x = (uint32_t)float_to_bf16((float)v[0]) | ((uint32_t)float_to_bf16((float)v[1]) << 16);
-        q.y = (uint32_t)float_to_bf16((float)v[2]) | ((uint32_t)float_to_bf16((float)v[3]) << 16);
-        *reinterpret_cast<uint2 *>(p) = q;
-    }
+template <> struct Raw<REP_SPLIT_BF16> {
+    static constexpr int CPL = 8;
+    uint4 h;
+    f4 a[2], b[2];
 };
+
+__device__ __forceinline__ uint32_t u4_at(const uint4 &v, int k) {
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void u4_set(uint4 &v, int k, uint32_t x) {
+    if (k == 0) v.x = x; else if (k == 1) v.y = x; else if (k == 2) v.z = x; else v.w = x;
+}
+
+template <int REP> __device__ __forceinline__ float hi_at(const Raw<REP> &t, int c);
+template <> __device__ __forceinline__ float hi_at<REP_SPLIT_F32>(const Raw<REP_SPLIT_F32> &t, int c) {
+    return t.h[c >> 2][c & 3];
+}
+template <> __device__ __forceinline__ float hi_at<REP_SPLIT_BF16>(const Raw<REP_SPLIT_BF16> &t, int c) {
+    const uint32_t w = u4_at(t.h, c >> 1);
+    return bf16_to_float((uint16_t)((c & 1) ? (w >> 16) : (w & 0xFFFFu)));
+}
+template <int REP> __device__ __forceinline__ void hi_set(Raw<REP> &t, int c, float v);
+template <> __device__ __forceinline__ void hi_set<REP_SPLIT_F32>(Raw<REP_SPLIT_F32> &t, int c, float v) {
+    t.h[c >> 2][c & 3] = v;
+}
+template <> __device__ __forceinline__ void hi_set<REP_SPLIT_BF16>(Raw<REP_SPLIT_BF16> &t, int c, float v) {
+    const uint32_t hv = float_to_bf16(v);
+    uint32_t w = u4_at(t.h, c >> 1);
+    w = (c & 1) ? ((w & 0xFFFFu) | (hv << 16)) : ((w & 0xFFFF0000u) | hv);
+    u4_set(t.h, c >> 1, w);
+}
 
 template <typename T> __device__ __forceinline__ T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
 
 // ---- the pair sweep -----------------------------------------------------------------------
-template <typename T, typename LT, int MODE, int MB>
-__global__ __launch_bounds__(256) void pass_kernel(PassArgs a, Geometry g) {
+template <typename T, int REP, int MODE, int MB>
+__global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry g) {
     constexpr int NP = 16 * MB;
-    constexpr int SX = NP + 1;                       // LDS row stride (elements)
-    constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER);
-    constexpr bool kResidual = (MODE != PASS_ADJ);
-    constexpr bool kStoreS = (MODE == PASS_RESID);
+    constexpr int SX = NP + 1;                       // LDS row stride (elements): odd, no bank aliasing
+    constexpr int BUF = kSuper * SX;
+    constexpr int NT = 64 * kWaves;                  // threads per workgroup
+    constexpr int XR = kSuper * NP / NT;             // staged X elements per thread
+    static_assert(XR * NT == kSuper * NP, "the X tile must split evenly over the threads");
+    constexpr int CPL = Raw<REP>::CPL;               // consecutive columns per lane
+    constexpr int NB = CPL / 4;                      // 16x16 MFMA blocks per tile
+    constexpr int TW = 4 * CPL;                      // tile width (columns)
+    constexpr int TPS = kSuper / TW;                 // tiles per super tile
+    constexpr bool kSplit = (REP != REP_F64);
+    constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER || MODE == PASS_REBASE);
+    constexpr bool kResidual = (MODE != PASS_ADJ && MODE != PASS_REBASE);
+    constexpr bool kColRed = kAdjoint || MODE == PASS_REPAIR;
+    constexpr bool kReadA = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT || MODE == PASS_REBASE);
+    constexpr bool kReadB = (MODE == PASS_STEP || MODE == PASS_REBASE);
+    constexpr bool kReadH = kSplit && kReadA;
+    constexpr bool kLoads = kReadA || kReadB;
     typedef typename Vec4<T>::type V4;
 
-    __shared__ T sX[kSuper * SX];
-    __shared__ T sY[kSuper];
-    __shared__ T sCol[kWaves * kSuper];
-    __shared__ int sArg[MODE == PASS_REPAIR ? kWaves * kSuper : 1];
+    __shared__ T sX[2 * BUF];
+    __shared__ T sY[2 * kSuper];
+    __shared__ T sCol[kColRed ? 2 * kWaves * kSuper : 1];
+    __shared__ int sArg[MODE == PASS_REPAIR ? 2 * kWaves * kSuper : 1];
     __shared__ double sRed[kWaves * kRed];
 
     const T *xhat = static_cast<const T *>(a.xhat);
     const T *xi = static_cast<const T *>(a.xi);
     const T *yv = static_cast<const T *>(a.yv);
     const T *dmy = static_cast<const T *>(a.dmy);
-    const LT *lam_a = static_cast<const LT *>(a.lam_a);
-    LT *lam_b = static_cast<LT *>(a.lam_b);
 
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, lr = l & 15, lq = l >> 4;
@@ -122,17 +140,22 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a, Geometry g) {
     const bool row_ok = i < g.N;
     const int cbeg = chunk * g.chunk_cols;
     const int cend = min(g.ld, cbeg + g.chunk_cols);
+    const int nsup = (cend - cbeg) / kSuper;
     const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L;
-    // Output rows of the 16x16x4 MFMA: the FP32 form gives lane group lq rows 4 lq + v, the FP64
-    // form rows 4 v + lq.  Feeding A-row rho from source row perm(rho) = 4 (rho % 4) + rho / 4
-    // in the FP64 case makes both end with rows 4 lq + v (four consecutive columns per lane).
-    const int arow = (sizeof(T) == 8) ? (((lr & 3) << 2) | (lr >> 2)) : lr;
+    // Output rows of the 16x16x4 MFMA: lane group g, item v receives row 4 g + v in the FP32 form
+    // and row 4 v + g in the FP64 form.  A-row rho is therefore fed the source that lane group
+    // g(rho), item v(rho) must see: feature 16 mb + 4 g + v in the adjoint contraction, column
+    // CPL g + 4 bb + v of block bb in the residual contraction.
+    const int rg = (sizeof(T) == 8) ? (lr & 3) : (lr >> 2);
+    const int rv = (sizeof(T) == 8) ? (lr >> 2) : (lr & 3);
+    const int arow = 4 * rg + rv;                    // feature row fed by this lane
+    const int acol = CPL * rg + rv;                  // tile column fed by this lane (block 0)
 
     // Row-constant operands: B of the residual contraction is Xi[i][4s + lq].
     T bxi[4 * MB];
 #pragma unroll
     for (int s = 0; s < 4 * MB; ++s)
-        bxi[s] = (kResidual && s < g.ks1) ? xi[(size_t)i * NP + 4 * s + lq] : (T)0;
+        bxi[s] = kResidual ? xi[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmy_i = kResidual ? dmy[i] : (T)0;
 
     V4 acc[MB];
@@ -141,76 +164,143 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a, Geometry g) {
     double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
 
     const size_t rowoff = (size_t)i * g.ld;
+    const double *pa64 = static_cast<const double *>(a.lam_a);
+    double *pb64 = static_cast<double *>(a.lam_b);
+    float *pa32 = static_cast<float *>(const_cast<void *>(a.lam_a));
+    float *pb32 = static_cast<float *>(a.lam_b);
+    float *phf = static_cast<float *>(a.lam_h);
+    uint16_t *phb = static_cast<uint16_t *>(a.lam_h);
 
-    for (int cst = cbeg; cst < cend; cst += kSuper) {
-        __syncthreads();
-        if ((kAdjoint || MODE == PASS_REPAIR) && cst > cbeg && tid < kSuper) {
-            const int j = cst - kSuper + tid;
-            if (MODE == PASS_REPAIR) {
-                double best = (double)sCol[tid];
-                int arg = sArg[tid];
-                for (int ww = 1; ww < kWaves; ++ww) {
-                    const double v = (double)sCol[ww * kSuper + tid];
-                    if (v < best) { best = v; arg = sArg[ww * kSuper + tid]; }
-                }
-                a.part_min[(size_t)strip * g.ld + j] = best;
-                a.part_arg[(size_t)strip * g.ld + j] = arg;
+    auto load_tile = [&](int j0, Raw<REP> &t) {
+        const size_t e = rowoff + j0;
+        if constexpr (REP == REP_F64) {
+            if (kReadA) t.p = ld_d4(pa64 + e);
+            if (kReadB) t.q = ld_d4(pb64 + e);
+        } else {
+            if constexpr (REP == REP_SPLIT_F32) {
+                if (kReadH) { t.h[0] = ld_f4(phf + e); t.h[1] = ld_f4(phf + e + 4); }
             } else {
-                T v = sCol[tid];
-                for (int ww = 1; ww < kWaves; ++ww) v += sCol[ww * kSuper + tid];
-                static_cast<T *>(a.part_col)[(size_t)strip * g.ld + j] = v;
+                if (kReadH) t.h = *reinterpret_cast<const uint4 *>(phb + e);
             }
+            if (kReadA) { t.a[0] = ld_f4(pa32 + e); t.a[1] = ld_f4(pa32 + e + 4); }
+            if (kReadB) { t.b[0] = ld_f4(pb32 + e); t.b[1] = ld_f4(pb32 + e + 4); }
         }
-        for (int e = tid; e < kSuper * NP; e += 256) {
+    };
+
+    // stage super tile 0 and prefetch the first two tiles' multipliers
+    if (nsup > 0) {
+        for (int e = tid; e < kSuper * NP; e += NT) {
             const int jj = e / NP, m = e - jj * NP;
-            sX[jj * SX + m] = xhat[(size_t)(cst + jj) * NP + m];
+            sX[jj * SX + m] = xhat[(size_t)(cbeg + jj) * NP + m];
         }
-        if (tid < kSuper) sY[tid] = kResidual ? yv[cst + tid] : (T)0;
-        __syncthreads();
+        if (tid < kSuper) sY[tid] = kResidual ? yv[cbeg + tid] : (T)0;
+    }
+    static_assert(TPS % 2 == 0, "the two-deep prefetch ring needs an even number of tiles per super tile");
+    Raw<REP> pf[2];
+    if (kLoads && nsup > 0) {
+        load_tile(cbeg + CPL * lq, pf[0]);
+        load_tile(cbeg + TW + CPL * lq, pf[1]);
+    }
+    __syncthreads();
+
+    for (int st = 0; st < nsup; ++st) {
+        const int cst = cbeg + st * kSuper;
+        const int b = st & 1;
+        const T *sXb = sX + b * BUF;
+        const T *sYb = sY + b * kSuper;
+        const bool more = st + 1 < nsup;
+
+        // register prefetch of the next super tile's locations (the last super tile re-reads its
+        // own rows instead, so the loads need no branch)
+        const int cnx = more ? cst + kSuper : cst;
+        T xr[XR];
+#pragma unroll
+        for (int q = 0; q < XR; ++q) xr[q] = xhat[(size_t)cnx * NP + tid + q * NT];
+        const T yr = kResidual ? yv[cnx + (tid & (kSuper - 1))] : (T)0;
+        __builtin_amdgcn_sched_barrier(0);
 
 #pragma unroll
-        for (int t = 0; t < kSuper / 16; ++t) {
-            const int jl = t * 16;
-            const int jc = jl + 4 * lq;              // local column of r = 0
-            const int j0 = cst + jc;                 // global column of r = 0
+        for (int t = 0; t < TPS; ++t) {
+            const int jl = t * TW;                   // local first column of the tile
+            const int jc = jl + CPL * lq;            // local column of c = 0 for this lane
+            const int j0 = cst + jc;                 // global column of c = 0
+            Raw<REP> cur = pf[t & 1];
+            if (kLoads) {
+                // two tiles ahead (possibly in the next super tile); past the end of the chunk the
+                // current tile is re-read instead, so the load needs no branch
+                const int jn = j0 + 2 * TW;
+                load_tile(jn < cend ? jn : j0, pf[t & 1]);
+            }
+            // keep the prefetch ahead of this tile's work (the scheduler would otherwise sink the
+            // loads below the epilogue, which then waits for them)
+            __builtin_amdgcn_sched_barrier(0);
 
-            V4 S = V4{0, 0, 0, 0};
-            if (kResidual) {
+            V4 S[NB];
 #pragma unroll
-                for (int s = 0; s < 4 * MB; ++s)
-                    if (s < g.ks1) S = mfma16(sX[(jl + arow) * SX + 4 * s + lq], bxi[s], S);
+            for (int bb = 0; bb < NB; ++bb) {
+                S[bb] = V4{0, 0, 0, 0};
+                if (kResidual) {
+                    // all 4 MB steps: Xi is zero beyond column n - 1, so the padded steps add zero
+                    // and the loop carries no branch (which would make the compiler drain the
+                    // prefetch queue at every join)
+#pragma unroll
+                    for (int s = 0; s < 4 * MB; ++s)
+                        S[bb] = mfma16(sXb[(jl + acol + 4 * bb) * SX + 4 * s + lq], bxi[s], S[bb]);
+                }
             }
 
-            T P[4] = {0, 0, 0, 0}, Q[4] = {0, 0, 0, 0};
-            if (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT)
-                Store<LT, T>::load4(lam_a + rowoff + j0, P);
-            if (MODE == PASS_STEP) Store<LT, T>::load4(lam_b + rowoff + j0, Q);
-
-            T out[4];
-            T newlam[4];
+            T out[CPL];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = j0 + r;
+            for (int c = 0; c < CPL; ++c) {
+                const int j = j0 + c;
                 const bool ok = row_ok && (j < g.N) && (j != i);
-                const T s = (sY[jc + r] + dmy_i) - S[r];
-                if (MODE == PASS_STEP) {
-                    const T lt = P[r] + bp * (P[r] - Q[r]);            // lam~^k
-                    T ln = lt - s * invL;                              // Step 2
+                const T s = (sYb[jc + c] + dmy_i) - S[c >> 2][c & 3];
+                if constexpr (MODE == PASS_STEP && REP == REP_F64) {
+                    const T P = (T)cur.p[c], Q = (T)cur.q[c];
+                    const T lt = P + bp * (P - Q);                       // lam~^k
+                    T ln = lt - s * invL;                                // Step 2
                     ln = ln > (T)0 ? ln : (T)0;
                     ln = ok ? ln : (T)0;
-                    ln = Store<LT, T>::quant(ln);                      // value as stored
-                    newlam[r] = ln;
-                    const T nx = ln + bn * (ln - P[r]);                // Step 4
-                    out[r] = ok ? nx : (T)0;
-                } else if (MODE == PASS_ADJ) {
-                    out[r] = ok ? P[r] : (T)0;
-                } else if (MODE == PASS_POWER) {
+                    cur.q[c] = (double)ln;                               // lam^k (stored below)
+                    const T nx = ln + bn * (ln - P);                     // Step 4
+                    out[c] = ok ? nx : (T)0;
+                } else if constexpr (MODE == PASS_STEP) {
+                    // lam = H + l: only the low parts move between re-basings
+                    const T H = (T)hi_at<REP>(cur, c);
+                    const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
+                    const T lt = l1 + bp * (l1 - l2);                    // low part of lam~^k
+                    T l0 = lt - s * invL;                                // Step 2 ...
+                    l0 = l0 > -H ? l0 : -H;                              // ... projected: H + l0 >= 0
+                    l0 = ok ? l0 : (T)0;
+                    cur.b[c >> 2][c & 3] = (float)l0;
+                    const T nx = l0 + bn * (l0 - l1);                    // low part of lam~^{k+1}
+                    out[c] = ok ? nx : (T)0;
+                } else if constexpr (MODE == PASS_ADJ) {
+                    T v;
+                    if constexpr (REP == REP_F64) v = (T)cur.p[c];
+                    else v = (T)((double)hi_at<REP>(cur, c) + (double)cur.a[c >> 2][c & 3]);
+                    out[c] = ok ? v : (T)0;
+                } else if constexpr (MODE == PASS_REBASE) {
+                    const double H = (double)hi_at<REP>(cur, c);
+                    const double lam0 = H + (double)cur.a[c >> 2][c & 3];   // lam^k
+                    const double lam1 = H + (double)cur.b[c >> 2][c & 3];   // lam^{k-1}
+                    float hn = (float)lam0;
+                    if (REP == REP_SPLIT_BF16) hn = bf16_to_float(float_to_bf16(hn));
+                    const double Hn = ok ? (double)hn : 0.0;
+                    cur.a[c >> 2][c & 3] = ok ? (float)(lam0 - Hn) : 0.f;
+                    cur.b[c >> 2][c & 3] = ok ? (float)(lam1 - Hn) : 0.f;
+                    hi_set<REP>(cur, c, (float)Hn);
+                    out[c] = (T)Hn;
+                } else if constexpr (MODE == PASS_POWER) {
                     const T z = ok ? s : (T)0;
-                    out[r] = z;
+                    out[c] = z;
                     red0 += (double)z * (double)z;
-                } else if (MODE == PASS_KKT) {
+                } else if constexpr (MODE == PASS_KKT) {
+                    double dl;
+                    if constexpr (REP == REP_F64) dl = cur.p[c];
+                    else dl = (double)hi_at<REP>(cur, c) + (double)cur.a[c >> 2][c & 3];
                     if (ok) {
-                        const double ds = (double)s, dl = (double)P[r];
+                        const double ds = (double)s;
                         const double mn = fabs(dl < ds ? dl : ds);
                         red0 = red0 > mn ? red0 : mn;
                         red1 = red1 > -ds ? red1 : -ds;
@@ -218,86 +308,121 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a, Geometry g) {
                         red2 += ng * ng;
                         red3 += dl * ds;
                     }
-                    out[r] = (T)0;
-                } else if (MODE == PASS_REPAIR) {
-                    out[r] = ok ? s : (T)INFINITY;
-                } else {  // PASS_RESID
-                    newlam[r] = ok ? s : (T)0;
-                    out[r] = (T)0;
+                    out[c] = (T)0;
+                } else if constexpr (MODE == PASS_REPAIR) {
+                    out[c] = ok ? s : (T)INFINITY;
+                } else {  // PASS_RESID (REP_F64)
+                    cur.q[c] = ok ? (double)s : 0.0;
+                    out[c] = (T)0;
                 }
             }
-            if (MODE == PASS_STEP || kStoreS) Store<LT, T>::store4(lam_b + rowoff + j0, newlam);
+            {
+                const size_t e = rowoff + j0;
+                if constexpr (REP == REP_F64) {
+                    if (MODE == PASS_STEP || MODE == PASS_RESID) *reinterpret_cast<d4 *>(pb64 + e) = cur.q;
+                } else {
+                    if (MODE == PASS_STEP || MODE == PASS_REBASE) {
+                        *reinterpret_cast<f4 *>(pb32 + e) = cur.b[0];
+                        *reinterpret_cast<f4 *>(pb32 + e + 4) = cur.b[1];
+                    }
+                    if (MODE == PASS_REBASE) {
+                        *reinterpret_cast<f4 *>(pa32 + e) = cur.a[0];
+                        *reinterpret_cast<f4 *>(pa32 + e + 4) = cur.a[1];
+                        if constexpr (REP == REP_SPLIT_F32) {
+                            *reinterpret_cast<f4 *>(phf + e) = cur.h[0];
+                            *reinterpret_cast<f4 *>(phf + e + 4) = cur.h[1];
+                        } else {
+                            *reinterpret_cast<uint4 *>(phb + e) = cur.h;
+                        }
+                    }
+                }
+            }
 
             if (kAdjoint) {
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        acc[mb] = mfma16(sX[(jc + r) * SX + 16 * mb + arow], out[r], acc[mb]);
-                T c[4] = {out[0], out[1], out[2], out[3]};
+                    for (int c = 0; c < CPL; ++c)
+                        acc[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out[c], acc[mb]);
+                T cs[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) cs[c] = out[c];
 #pragma unroll
                 for (int m = 1; m < 16; m <<= 1)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) c[r] += shfl_xor(c[r], m);
+                    for (int c = 0; c < CPL; ++c) cs[c] += shfl_xor(cs[c], m);
                 if (lr == 0) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sCol[w * kSuper + jc + r] = c[r];
+                    for (int c = 0; c < CPL; ++c) sCol[(b * kWaves + w) * kSuper + jc + c] = cs[c];
                 }
             } else if (MODE == PASS_REPAIR) {
                 // column minimum over the 16 rows of this wave, lowest row on ties
-                T v[4] = {out[0], out[1], out[2], out[3]};
-                int arg[4] = {i, i, i, i};
+                T v[CPL];
+                int arg[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) { v[c] = out[c]; arg[c] = i; }
 #pragma unroll
                 for (int m = 1; m < 16; m <<= 1)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const T ov = shfl_xor(v[r], m);
-                        const int oa = __shfl_xor(arg[r], m, 64);
-                        if (ov < v[r] || (ov == v[r] && oa < arg[r])) { v[r] = ov; arg[r] = oa; }
+                    for (int c = 0; c < CPL; ++c) {
+                        const T ov = shfl_xor(v[c], m);
+                        const int oa = __shfl_xor(arg[c], m, 64);
+                        if (ov < v[c] || (ov == v[c] && oa < arg[c])) { v[c] = ov; arg[c] = oa; }
                     }
                 if (lr == 0) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        sCol[w * kSuper + jc + r] = v[r];
-                        sArg[w * kSuper + jc + r] = arg[r];
+                    for (int c = 0; c < CPL; ++c) {
+                        sCol[(b * kWaves + w) * kSuper + jc + c] = v[c];
+                        sArg[(b * kWaves + w) * kSuper + jc + c] = arg[c];
                     }
                 }
             }
         }
-    }
 
-    // last super tile's column partials
-    __syncthreads();
-    if ((kAdjoint || MODE == PASS_REPAIR) && tid < kSuper && cend > cbeg) {
-        const int j = cend - kSuper + tid;
-        if (MODE == PASS_REPAIR) {
-            double best = (double)sCol[tid];
-            int arg = sArg[tid];
-            for (int ww = 1; ww < kWaves; ++ww) {
-                const double v = (double)sCol[ww * kSuper + tid];
-                if (v < best) { best = v; arg = sArg[ww * kSuper + tid]; }
+        // the next super tile's locations go to the other buffer
+        if (more) {
+            T *sXn = sX + (b ^ 1) * BUF;
+#pragma unroll
+            for (int q = 0; q < XR; ++q) {
+                const int e = tid + q * NT;
+                const int jj = e / NP, m = e - jj * NP;
+                sXn[jj * SX + m] = xr[q];
             }
-            a.part_min[(size_t)strip * g.ld + j] = best;
-            a.part_arg[(size_t)strip * g.ld + j] = arg;
-        } else {
-            T v = sCol[tid];
-            for (int ww = 1; ww < kWaves; ++ww) v += sCol[ww * kSuper + tid];
-            static_cast<T *>(a.part_col)[(size_t)strip * g.ld + j] = v;
+            if (tid < kSuper) sY[(b ^ 1) * kSuper + tid] = yr;
+        }
+        __syncthreads();
+        // column partials of this super tile (buffer b is not written again before the next barrier)
+        if (kColRed && tid < kSuper) {
+            const int j = cst + tid;
+            const int base = b * kWaves * kSuper;
+            if (MODE == PASS_REPAIR) {
+                double best = (double)sCol[base + tid];
+                int arg = sArg[base + tid];
+                for (int ww = 1; ww < kWaves; ++ww) {
+                    const double v = (double)sCol[base + ww * kSuper + tid];
+                    if (v < best) { best = v; arg = sArg[base + ww * kSuper + tid]; }
+                }
+                a.part_min[(size_t)strip * g.ld + j] = best;
+                a.part_arg[(size_t)strip * g.ld + j] = arg;
+            } else {
+                T v = sCol[base + tid];
+                for (int ww = 1; ww < kWaves; ++ww) v += sCol[base + ww * kSuper + tid];
+                static_cast<T *>(a.part_col)[(size_t)strip * g.ld + j] = v;
+            }
         }
     }
 
     if (kAdjoint) {
-        // D layout: lane (lr, lq) holds rows m = 16 mb + 4 lq + r of (Lam Xhat)^T for row i.
+        // D layout: lane (lr, lq) holds rows m = 16 mb + 4 lq + v of (Lam Xhat)^T for row i.
         T *pacc = static_cast<T *>(a.part_acc) + ((size_t)chunk * g.Nr + i) * NP;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-            T v[4] = {acc[mb][0], acc[mb][1], acc[mb][2], acc[mb][3]};
             if (sizeof(T) == 8) {
                 *reinterpret_cast<d4 *>(reinterpret_cast<double *>(pacc) + 16 * mb + 4 * lq) =
-                    d4{(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+                    d4{(double)acc[mb][0], (double)acc[mb][1], (double)acc[mb][2], (double)acc[mb][3]};
             } else {
                 *reinterpret_cast<f4 *>(reinterpret_cast<float *>(pacc) + 16 * mb + 4 * lq) =
-                    f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+                    f4{(float)acc[mb][0], (float)acc[mb][1], (float)acc[mb][2], (float)acc[mb][3]};
             }
         }
     }
@@ -328,6 +453,11 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a, Geometry g) {
     }
 }
 
+static int env_int(const char *name, int def) {
+    const char *v = getenv(name);
+    return v ? atoi(v) : def;
+}
+
 Geometry make_geometry(int N, int n) {
     Geometry g;
     g.N = N;
@@ -336,57 +466,65 @@ Geometry make_geometry(int N, int n) {
     g.NP = 16 * g.MB;
     g.ks1 = (n + 3) / 4;
     g.Nr = ((N + kRows - 1) / kRows) * kRows;
+    g.Nr = ((g.Nr + kSuper - 1) / kSuper) * kSuper;
     g.ld = g.Nr;
     g.strips = g.Nr / kRows;
     const int supers = g.ld / kSuper;
-    int chunks = supers < 8 ? supers : 8;
+    const int want = env_int("CR_CHUNKS", 8);
+    int chunks = supers < want ? supers : want;
+    if (chunks < 1) chunks = 1;
     int per = (supers + chunks - 1) / chunks;
     g.chunk_cols = per * kSuper;
     g.chunks = (g.ld + g.chunk_cols - 1) / g.chunk_cols;
     return g;
 }
 
-template <typename T, typename LT, int MODE>
+template <typename T, int REP, int MODE>
 static hipError_t launch_mb(const Geometry &g, const PassArgs &a, hipStream_t st) {
-    dim3 grid(g.grid()), block(256);
+    dim3 grid(g.grid()), block(64 * kWaves);
     switch (g.MB) {
-    case 1: hipLaunchKernelGGL((pass_kernel<T, LT, MODE, 1>), grid, block, 0, st, a, g); break;
-    case 2: hipLaunchKernelGGL((pass_kernel<T, LT, MODE, 2>), grid, block, 0, st, a, g); break;
-    case 3: hipLaunchKernelGGL((pass_kernel<T, LT, MODE, 3>), grid, block, 0, st, a, g); break;
-    case 4: hipLaunchKernelGGL((pass_kernel<T, LT, MODE, 4>), grid, block, 0, st, a, g); break;
+    case 1: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 1>), grid, block, 0, st, a, g); break;
+    case 2: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 2>), grid, block, 0, st, a, g); break;
+    case 3: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 3>), grid, block, 0, st, a, g); break;
+    case 4: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 4>), grid, block, 0, st, a, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamType lt, const PassArgs &a,
+hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, const PassArgs &a,
                        hipStream_t st) {
     if (g.MB < 1 || g.MB > kMaxMB) return hipErrorInvalidValue;
     switch (mode) {
     case PASS_STEP:
-        if (!fp32 && lt == LAM_F64) return launch_mb<double, double, PASS_STEP>(g, a, st);
-        if (fp32 && lt == LAM_F32) return launch_mb<float, float, PASS_STEP>(g, a, st);
-        if (fp32 && lt == LAM_BF16) return launch_mb<float, bf16_t, PASS_STEP>(g, a, st);
+        if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_STEP>(g, a, st);
+        if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_STEP>(g, a, st);
+        if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_STEP>(g, a, st);
         return hipErrorInvalidValue;
     case PASS_ADJ:
         if (fp32) return hipErrorInvalidValue;
-        if (lt == LAM_F64) return launch_mb<double, double, PASS_ADJ>(g, a, st);
-        if (lt == LAM_F32) return launch_mb<double, float, PASS_ADJ>(g, a, st);
-        return launch_mb<double, bf16_t, PASS_ADJ>(g, a, st);
+        if (rep == REP_F64) return launch_mb<double, REP_F64, PASS_ADJ>(g, a, st);
+        if (rep == REP_SPLIT_F32) return launch_mb<double, REP_SPLIT_F32, PASS_ADJ>(g, a, st);
+        return launch_mb<double, REP_SPLIT_BF16, PASS_ADJ>(g, a, st);
     case PASS_KKT:
         if (fp32) return hipErrorInvalidValue;
-        if (lt == LAM_F64) return launch_mb<double, double, PASS_KKT>(g, a, st);
-        if (lt == LAM_F32) return launch_mb<double, float, PASS_KKT>(g, a, st);
-        return launch_mb<double, bf16_t, PASS_KKT>(g, a, st);
+        if (rep == REP_F64) return launch_mb<double, REP_F64, PASS_KKT>(g, a, st);
+        if (rep == REP_SPLIT_F32) return launch_mb<double, REP_SPLIT_F32, PASS_KKT>(g, a, st);
+        return launch_mb<double, REP_SPLIT_BF16, PASS_KKT>(g, a, st);
+    case PASS_REBASE:
+        if (fp32) return hipErrorInvalidValue;
+        if (rep == REP_SPLIT_F32) return launch_mb<double, REP_SPLIT_F32, PASS_REBASE>(g, a, st);
+        if (rep == REP_SPLIT_BF16) return launch_mb<double, REP_SPLIT_BF16, PASS_REBASE>(g, a, st);
+        return hipErrorInvalidValue;
     case PASS_POWER:
         if (fp32) return hipErrorInvalidValue;
-        return launch_mb<double, double, PASS_POWER>(g, a, st);
+        return launch_mb<double, REP_F64, PASS_POWER>(g, a, st);
     case PASS_REPAIR:
         if (fp32) return hipErrorInvalidValue;
-        return launch_mb<double, double, PASS_REPAIR>(g, a, st);
+        return launch_mb<double, REP_F64, PASS_REPAIR>(g, a, st);
     case PASS_RESID:
-        if (fp32 || lt != LAM_F64) return hipErrorInvalidValue;
-        return launch_mb<double, double, PASS_RESID>(g, a, st);
+        if (fp32 || rep != REP_F64) return hipErrorInvalidValue;
+        return launch_mb<double, REP_F64, PASS_RESID>(g, a, st);
     }
     return hipErrorInvalidValue;
 }
@@ -421,7 +559,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a, Geometry 
     for (int m = 1; m < 16; m <<= 1) csum += __shfl_xor(csum, m, 16);
 
     const bool valid = i < g.N;
-    const double u = csum - rsum;
+    double u = csum - rsum;
+    if (a.ubase) u += a.ubase[i];
     const double yi = valid ? (a.power ? u : a.ybar[i] + u) : 0.0;
     double xv[MB];
     double d = 0.0, xsq = 0.0;
@@ -432,6 +571,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a, Geometry 
         if (valid && m < g.n) {
             const double xm = a.xf[(size_t)i * NP + m];
             v = rsum * xm - lx[mb];
+            if (a.wbase) v += a.wbase[(size_t)i * NP + m];
             if (!a.power) v *= a.inv_delta;
             d += v * xm;
             xsq += v * v;
@@ -522,55 +662,66 @@ hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dm
     return hipGetLastError();
 }
 
-// ---- conversions and packing ------------------------------------------------------------------
-__device__ __forceinline__ double load_lam(const void *p, LamType t, size_t e) {
-    if (t == LAM_F64) return static_cast<const double *>(p)[e];
-    if (t == LAM_F32) return (double)static_cast<const float *>(p)[e];
+// ---- representation changes -------------------------------------------------------------------
+__device__ __forceinline__ double hi_load(const void *p, LamRep rep, size_t e) {
+    if (rep == REP_SPLIT_F32) return (double)static_cast<const float *>(p)[e];
     return (double)bf16_to_float(static_cast<const uint16_t *>(p)[e]);
 }
-__device__ __forceinline__ void store_lam(void *p, LamType t, size_t e, double v) {
-    if (t == LAM_F64) static_cast<double *>(p)[e] = v;
-    else if (t == LAM_F32) static_cast<float *>(p)[e] = (float)v;
-    else static_cast<uint16_t *>(p)[e] = float_to_bf16((float)v);
-}
 
-__global__ void convert_kernel(const void *src, LamType stt, void *dst, LamType dt, size_t tot) {
+__global__ void merge_kernel(LamRep rep, const void *hi, const float *lo, double *dst, size_t tot) {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x)
-        store_lam(dst, dt, e, load_lam(src, stt, e));
+        dst[e] = hi_load(hi, rep, e) + (double)lo[e];
 }
 
-hipError_t launch_convert(const Geometry &g, const void *src, LamType stt, void *dst, LamType dt,
-                          hipStream_t st) {
-    const size_t tot = (size_t)g.Nr * g.ld;
-    hipLaunchKernelGGL(convert_kernel, dim3(8192), dim3(256), 0, st, src, stt, dst, dt, tot);
+hipError_t launch_merge(const Geometry &g, LamRep rep, const void *hi, const float *lo, double *dst, hipStream_t st) {
+    if (rep == REP_F64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(merge_kernel, dim3(8192), dim3(256), 0, st, rep, hi, lo, dst, (size_t)g.Nr * g.ld);
     return hipGetLastError();
 }
 
-__global__ void pack_kernel(const double *dense, void *dst, LamType lt, int N, int Nr, int ld) {
+__global__ void pack_kernel(const double *dense, LamRep rep, void *main, float *lo, int N, int Nr, int ld) {
     const size_t tot = (size_t)Nr * ld;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / ld), j = (int)(e - (size_t)i * ld);
         double v = 0.0;
         if (i < N && j < N && i != j) v = dense[(size_t)i * N + j];
-        store_lam(dst, lt, e, v);
+        if (rep == REP_F64) {
+            static_cast<double *>(main)[e] = v;
+        } else {
+            float h = (float)v;
+            if (rep == REP_SPLIT_BF16) {
+                const uint16_t hb = float_to_bf16(h);
+                static_cast<uint16_t *>(main)[e] = hb;
+                h = bf16_to_float(hb);
+            } else {
+                static_cast<float *>(main)[e] = h;
+            }
+            lo[e] = (float)(v - (double)h);
+        }
     }
 }
 
-__global__ void unpack_kernel(const void *src, LamType lt, double *dense, int N, int ld) {
+__global__ void unpack_kernel(LamRep rep, const void *main, const float *lo, double *dense, int N, int ld) {
     const size_t tot = (size_t)N * N;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / N), j = (int)(e - (size_t)i * N);
-        dense[e] = (i == j) ? 0.0 : load_lam(src, lt, (size_t)i * ld + j);
+        const size_t f = (size_t)i * ld + j;
+        double v;
+        if (rep == REP_F64) v = static_cast<const double *>(main)[f];
+        else v = hi_load(main, rep, f) + (double)lo[f];
+        dense[e] = (i == j) ? 0.0 : v;
     }
 }
 
-hipError_t launch_pack_lambda(const Geometry &g, const double *dense, void *dst, LamType lt, hipStream_t st) {
-    hipLaunchKernelGGL(pack_kernel, dim3(8192), dim3(256), 0, st, dense, dst, lt, g.N, g.Nr, g.ld);
+hipError_t launch_pack_lambda(const Geometry &g, const double *dense, LamRep rep, void *main, float *lo,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(pack_kernel, dim3(8192), dim3(256), 0, st, dense, rep, main, lo, g.N, g.Nr, g.ld);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_lambda(const Geometry &g, const void *src, LamType lt, double *dense, hipStream_t st) {
-    hipLaunchKernelGGL(unpack_kernel, dim3(8192), dim3(256), 0, st, src, lt, dense, g.N, g.ld);
+hipError_t launch_unpack_lambda(const Geometry &g, LamRep rep, const void *main, const float *lo, double *dense,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(unpack_kernel, dim3(8192), dim3(256), 0, st, rep, main, lo, dense, g.N, g.ld);
     return hipGetLastError();
 }
 
