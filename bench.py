@@ -96,6 +96,37 @@ def cpu_baseline(x, ybar, delta: float, L: float, iters: int) -> dict:
                       f"n={x.shape[1]} fit in the FP64 numpy oracle, L fixed; {dt:.1f} s"}
 
 
+def run_serving(cr, W, count: int, slots: int, precision: str) -> dict:
+    """Replay a Poisson stream of fit requests through the continuous-batching context.
+
+    Requests (N log-uniform in [100, 6000], n uniform in 2..32, ||x||^2 or 8-piece log-sum-exp,
+    noise 0.1, delta 1e-3, KKT tol 1e-4) are submitted at their arrival times; latency is completion
+    minus submission as measured by the library.
+    """
+    import numpy as np
+    reqs = W.serving_requests(count=count, seed=0)
+    opt = cr.Options(precision=precision)
+    ids = []
+    with cr.Server(max_slots=slots) as srv:
+        t0 = time.perf_counter()
+        for r in reqs:
+            wait = r.arrival_s - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            ids.append(srv.submit(r.x, r.ybar, r.delta, r.tol, opt))
+        res = [srv.wait(i) for i in ids]
+        t_end = time.perf_counter() - t0
+    lat = np.array([r.extra["latency_s"] for r in res])
+    iters = np.array([r.report["iters"] for r in res])
+    conv = sum(1 for r in res if r.status == cr.CR_OK)
+    log(f"serving: {count} fits in {t_end:.1f} s, p50 {np.percentile(lat, 50):.3f} s, p99 {np.percentile(lat, 99):.3f} s")
+    return {"requests": count, "slots": slots, "precision": precision, "wall_s": round(t_end, 3),
+            "fits_per_s": round(count / t_end, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "mean_iters": float(iters.mean()),
+            "converged": conv, "arrival_span_s": round(reqs[-1].arrival_s, 3),
+            "N_range": [int(min(r.x.shape[0] for r in reqs)), int(max(r.x.shape[0] for r in reqs))]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +140,9 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--max-iters", type=int, default=0,
                     help="cap the iterations of each fit (short profiling runs of the same kernels)")
+    ap.add_argument("--serving", type=int, default=0, metavar="K",
+                    help="also replay K requests of the serving stream (Poisson, 50/s) and report latency")
+    ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,6 +257,8 @@ def main() -> int:
                    "seed": args.seed},
         "roofline": roofline,
     }
+    if args.serving > 0:
+        out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations at N={wl.N} ...")
         out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters)

@@ -179,6 +179,8 @@ int64_t cr_solver_iterations(const cr_solver *s);
 
 /* Copies lam^k (N x N, FP64, host) out. */
 int cr_solver_get_lambda(cr_solver *s, double *lambda);
+/* Copies rows [row0, row0 + nrows) of lam^k (nrows x N, FP64, host) out; rows must lie in [0, N). */
+int cr_solver_get_lambda_rows(cr_solver *s, int64_t row0, int64_t nrows, double *rows);
 /* FP64 closed-form eta(lam^k) = (ybar + A1^T lam^k, A2^T lam^k / delta) to host. */
 int cr_solver_get_primal(cr_solver *s, double *y, double *xi);
 /* FP64 stopping report of lam^k (and the certificate if opt.certificate). */
@@ -208,6 +210,11 @@ int cr_poll(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
 /* Blocking version of cr_poll. */
 int cr_wait(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
             double *latency_s);
+/* Device bytes the serving context reserves for one fit of this shape and precision (the two
+ * multiplier iterates, the partial sums and O(N n) vectors; mixed modes include the FP64 pair a
+ * promotion would allocate).  Admission requires the sum over running fits to fit the budget. */
+size_t cr_fit_state_bytes(int64_t N, int64_t n, int32_t precision);
+
 /* Counters: fits queued, running, finished; bytes of multiplier state resident. */
 int cr_ctx_stats(cr_ctx *ctx, int64_t *queued, int64_t *running, int64_t *finished,
                  size_t *resident_bytes);

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcr.so")
+LIB_PATH = os.environ.get("CR_LIB_PATH") or os.path.join(_HERE, "libcr.so")
 
 CR_OK, CR_EINVAL, CR_ENOMEM, CR_ENOCONV, CR_ENUMERIC, CR_EDEVICE, CR_EAGAIN, CR_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
@@ -117,6 +117,7 @@ def load() -> C.CDLL:
         "cr_solver_promote": (C.c_int, [vp]),
         "cr_solver_iterations": (i64, [vp]),
         "cr_solver_get_lambda": (C.c_int, [vp, vp]),
+        "cr_solver_get_lambda_rows": (C.c_int, [vp, i64, i64, vp]),
         "cr_solver_get_primal": (C.c_int, [vp, vp, vp]),
         "cr_solver_report": (C.c_int, [vp, _P(CRReport)]),
         "cr_op_residual": (C.c_int, [i64, i64, vp, vp, vp, vp, C.c_int]),
@@ -127,6 +128,7 @@ def load() -> C.CDLL:
         "cr_poll": (C.c_int, [vp, i64, vp, vp, _P(CRReport), _P(d)]),
         "cr_wait": (C.c_int, [vp, i64, vp, vp, _P(CRReport), _P(d)]),
         "cr_ctx_stats": (C.c_int, [vp, _P(i64), _P(i64), _P(i64), _P(C.c_size_t)]),
+        "cr_fit_state_bytes": (C.c_size_t, [i64, i64, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -309,6 +311,11 @@ class Solver:
         _check(load().cr_solver_get_lambda(self._h, _ptr(out)), "get_lambda")
         return out
 
+    def lam_rows(self, row0: int, nrows: int) -> np.ndarray:
+        out = np.empty((nrows, self.N))
+        _check(load().cr_solver_get_lambda_rows(self._h, row0, nrows, _ptr(out)), "get_lambda_rows")
+        return out
+
     def primal(self) -> tuple[np.ndarray, np.ndarray]:
         y = np.empty(self.N)
         xi = np.empty((self.N, self.n))
@@ -342,6 +349,11 @@ def op_adjoint(x, lam, device: int = 0):
     _check(load().cr_op_adjoint(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(lam.data_ptr()), C.c_void_p(u.data_ptr()),
                                 C.c_void_p(w.data_ptr()), device), "op_adjoint")
     return u, w
+
+
+def state_bytes(N: int, n: int, precision: str = "fp64") -> int:
+    """Device bytes a serving context reserves for one fit (cr_fit_state_bytes)."""
+    return int(load().cr_fit_state_bytes(N, n, PRECISIONS[precision]))
 
 
 class Server:

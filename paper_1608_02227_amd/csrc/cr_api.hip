@@ -169,7 +169,14 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     s->device = opt.device;
     s->opt = opt;
     s->delta = delta;
-    s->g = make_geometry((int)N, (int)n);
+    {
+        // workgroups resident at once: one per compute unit at the pass kernel's occupancy
+        hipDeviceProp_t prop;
+        int cus = 256;
+        if (hipGetDeviceProperties(&prop, opt.device) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+        s->g = make_geometry((int)N, (int)n, cus);
+    }
     s->precision = opt.precision;
     s->rep = rep_of(opt.precision);
     s->fp32pass = opt.precision != CR_FP64;
@@ -669,6 +676,21 @@ extern "C" int cr_solver_get_lambda(cr_solver *s, double *lambda) {
     CR_HIP(launch_unpack_lambda(s->g, s->rep, s->rep == REP_F64 ? s->lam[s->cur] : s->lam_hi,
                                 (const float *)s->lam[s->cur], d, s->stream));
     CR_HIP(hipMemcpyAsync(lambda, d, bytes, hipMemcpyDeviceToHost, s->stream));
+    CR_HIP(hipStreamSynchronize(s->stream));
+    s->release(d);
+    return CR_OK;
+}
+
+extern "C" int cr_solver_get_lambda_rows(cr_solver *s, int64_t row0, int64_t nrows, double *rows) {
+    if (!s || !rows || row0 < 0 || nrows < 1 || row0 + nrows > s->g.N) return CR_EINVAL;
+    CR_HIP(hipSetDevice(s->device));
+    double *d = nullptr;
+    const size_t bytes = (size_t)nrows * s->g.N * 8;
+    int rc = s->alloc((void **)&d, bytes);
+    if (rc) return rc;
+    CR_HIP(launch_unpack_rows(s->g, s->rep, s->rep == REP_F64 ? s->lam[s->cur] : s->lam_hi,
+                              (const float *)s->lam[s->cur], (int)row0, (int)nrows, d, s->stream));
+    CR_HIP(hipMemcpyAsync(rows, d, bytes, hipMemcpyDeviceToHost, s->stream));
     CR_HIP(hipStreamSynchronize(s->stream));
     s->release(d);
     return CR_OK;

@@ -30,7 +30,7 @@ enum PassMode : int {
 
 // Tiling shared by host and device code.
 #ifndef CR_WAVES
-#define CR_WAVES 4
+#define CR_WAVES 8
 #endif
 constexpr int kWaves = CR_WAVES;         // waves per workgroup
 constexpr int kRows = 16 * kWaves;       // rows i per workgroup (one 16-row MFMA block per wave)
@@ -52,7 +52,11 @@ struct Geometry {
     int grid() const { return strips * chunks; }
 };
 
-Geometry make_geometry(int N, int n);
+// Tiling of an N-point fit.  `slots` is the number of workgroups the device runs at once (compute
+// units x resident workgroups per unit); the column chunk count is chosen so that the workgroup
+// count fills whole rounds of `slots` as evenly as possible, preferring fewer chunks (less
+// partial-sum traffic).  slots <= 0 uses 256.
+Geometry make_geometry(int N, int n, int slots = 0);
 
 // One sweep over all pairs.  T is the arithmetic type of the contraction and epilogue; the
 // multipliers use representation `rep`.  Pointer roles (all device, padded as in Geometry):
@@ -134,6 +138,9 @@ hipError_t launch_pack_lambda(const Geometry &g, const double *dense, LamRep rep
                               hipStream_t st);
 hipError_t launch_unpack_lambda(const Geometry &g, LamRep rep, const void *main, const float *lo,
                                 double *dense, hipStream_t st);
+// Rows [row0, row0 + nrows) only, into a dense nrows x N FP64 array.
+hipError_t launch_unpack_rows(const Geometry &g, LamRep rep, const void *main, const float *lo, int row0,
+                              int nrows, double *dense, hipStream_t st);
 
 // Builds xhat (FP64 x - mu, ones in column n, zero padding) and optionally its float copy
 // from dense N x n locations, and pads ybar (may be null).  mu may be null (no shift).

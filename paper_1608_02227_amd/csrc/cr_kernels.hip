@@ -458,7 +458,7 @@ static int env_int(const char *name, int def) {
     return v ? atoi(v) : def;
 }
 
-Geometry make_geometry(int N, int n) {
+Geometry make_geometry(int N, int n, int slots) {
     Geometry g;
     g.N = N;
     g.n = n;
@@ -470,10 +470,23 @@ Geometry make_geometry(int N, int n) {
     g.ld = g.Nr;
     g.strips = g.Nr / kRows;
     const int supers = g.ld / kSuper;
-    const int want = env_int("CR_CHUNKS", 8);
-    int chunks = supers < want ? supers : want;
-    if (chunks < 1) chunks = 1;
-    int per = (supers + chunks - 1) / chunks;
+    if (slots <= 0) slots = 256;
+    int best = 1;
+    double best_eff = -1.0;
+    const int forced = env_int("CR_CHUNKS", 0);
+    for (int c = 1; c <= 16 && c <= supers; ++c) {
+        const int per = (supers + c - 1) / c;
+        const int chunks = (supers + per - 1) / per;
+        if (chunks != c) continue;                      // same split as a smaller count
+        const long wgs = (long)g.strips * chunks;
+        const long rounds = (wgs + slots - 1) / slots;
+        // balance: the last column chunk may be shorter than the others
+        const double col_eff = (double)supers / ((double)chunks * per);
+        const double eff = (double)wgs / ((double)rounds * slots) * col_eff;
+        if (eff > best_eff + 0.02) { best_eff = eff; best = c; }
+    }
+    if (forced > 0) best = forced < supers ? forced : supers;
+    const int per = (supers + best - 1) / best;
     g.chunk_cols = per * kSuper;
     g.chunks = (g.ld + g.chunk_cols - 1) / g.chunk_cols;
     return g;
@@ -711,6 +724,26 @@ __global__ void unpack_kernel(LamRep rep, const void *main, const float *lo, dou
         else v = hi_load(main, rep, f) + (double)lo[f];
         dense[e] = (i == j) ? 0.0 : v;
     }
+}
+
+__global__ void unpack_rows_kernel(LamRep rep, const void *main, const float *lo, double *dense, int N, int ld,
+                                   int row0, int nrows) {
+    const size_t tot = (size_t)nrows * N;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / N), j = (int)(e - (size_t)r * N);
+        const int i = row0 + r;
+        const size_t f = (size_t)i * ld + j;
+        double v;
+        if (rep == REP_F64) v = static_cast<const double *>(main)[f];
+        else v = hi_load(main, rep, f) + (double)lo[f];
+        dense[e] = (i == j) ? 0.0 : v;
+    }
+}
+
+hipError_t launch_unpack_rows(const Geometry &g, LamRep rep, const void *main, const float *lo, int row0, int nrows,
+                              double *dense, hipStream_t st) {
+    hipLaunchKernelGGL(unpack_rows_kernel, dim3(1024), dim3(256), 0, st, rep, main, lo, dense, g.N, g.ld, row0, nrows);
+    return hipGetLastError();
 }
 
 hipError_t launch_pack_lambda(const Geometry &g, const double *dense, LamRep rep, void *main, float *lo,

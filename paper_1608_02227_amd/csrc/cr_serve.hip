@@ -111,6 +111,13 @@ struct cr_ctx {
     }
 };
 
+extern "C" size_t cr_fit_state_bytes(int64_t N, int64_t n, int32_t precision) {
+    if (N < 1 || n < 1 || n + 1 > 16 * cr::kMaxMB || precision < CR_FP64 || precision > CR_MIXED_BF16) return 0;
+    size_t b = cr_state_bytes(N, n, precision);
+    if (precision != CR_FP64) b += cr_state_bytes(N, n, CR_FP64);   // promotion peak
+    return b;
+}
+
 extern "C" int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, cr_ctx **out) {
     if (!out || max_slots < 1 || max_slots > 64) return CR_EINVAL;
     *out = nullptr;
@@ -166,8 +173,7 @@ extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const
     r->delta = delta;
     r->tol = tol;
     if (opt) r->opt = *opt; else cr_default_options(&r->opt);
-    r->bytes = cr_state_bytes(N, n, r->opt.precision);
-    if (r->opt.precision != CR_FP64) r->bytes += cr_state_bytes(N, n, CR_FP64);   // promotion peak
+    r->bytes = cr_fit_state_bytes(N, n, r->opt.precision);
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(c->mu);
     if (r->bytes > c->budget) return CR_ENOMEM;

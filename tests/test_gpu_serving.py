@@ -1,0 +1,92 @@
+"""Serving (continuous batching) on the GPU: results are the same alone and in a mix, admission
+respects the slot count and the byte budget, and oversize requests are refused."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1608_02227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return torch
+
+
+def _requests(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(count):
+        N = int(rng.integers(90, 700))
+        n = int(rng.integers(2, 33))
+        if r % 2:
+            x, yb = W.sq_norm(N, n, 0.1, 1000 + r)
+        else:
+            x, yb = W.log_sum_exp_affine(N, n, 8, 0.1, 1000 + r, x_dist="uniform")
+        out.append((x, yb))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "fp64"])
+def test_mix_equals_alone(cr, torch_dev, precision):
+    reqs = _requests(8, 3)
+    opt = cr.Options(precision=precision, max_iters=3000)
+    alone = [cr.fit(x, yb, 1e-3, 1e-3, opt) for (x, yb) in reqs]
+    with cr.Server(max_slots=4) as srv:
+        ids = [srv.submit(x, yb, 1e-3, 1e-3, opt) for (x, yb) in reqs]
+        mixed = [srv.wait(i) for i in ids]
+    for a, m in zip(alone, mixed):
+        np.testing.assert_array_equal(a.y, m.y)
+        np.testing.assert_array_equal(a.xi, m.xi)
+        assert a.report["iters"] == m.report["iters"]
+        assert m.extra["latency_s"] > 0.0
+
+
+def test_admission_by_bytes_and_slots(cr, torch_dev):
+    reqs = [W.sq_norm(400, 5, 0.1, 40 + r) for r in range(5)]     # equal shapes: equal reservations
+    one = cr.state_bytes(400, 5, "fp64")
+    opt = cr.Options(max_iters=400)
+    with cr.Server(max_slots=4, byte_budget=one + one // 2) as srv:   # room for one fit at a time
+        ids = [srv.submit(x, yb, 1e-3, 1e-6, opt) for (x, yb) in reqs]
+        peak = 0
+        while True:
+            st = srv.stats()
+            peak = max(peak, st["running"])
+            assert st["resident_bytes"] <= one + one // 2
+            if st["finished"] == len(ids):
+                break
+            time.sleep(0.002)
+        res = [srv.wait(i) for i in ids]
+    assert peak == 1
+    # strict FIFO with room for one fit: each request waits for all earlier ones, so latencies
+    # (measured from near-simultaneous submissions) grow with the submission order
+    lat = [r.extra["latency_s"] for r in res]
+    assert all(b > a for a, b in zip(lat, lat[1:]))
+    assert all(r.report["iters"] == 400 for r in res)
+
+
+def test_oversize_request_is_refused(cr, torch_dev):
+    x, yb = W.sq_norm(300, 3, 0.1, 0)
+    with cr.Server(max_slots=2, byte_budget=1 << 20) as srv:
+        with pytest.raises(cr.CRError) as e:
+            srv.submit(x, yb, 1e-3, 1e-4)
+        assert e.value.code == cr.CR_ENOMEM
+
+
+def test_poll_and_stats(cr, torch_dev):
+    x, yb = W.sq_norm(150, 2, 0.1, 5)
+    with cr.Server(max_slots=1) as srv:
+        rid = srv.submit(x, yb, 1e-3, 1e-3, cr.Options(max_iters=2000))
+        got = None
+        for _ in range(20000):
+            got = srv.poll(rid)
+            if got is not None:
+                break
+            time.sleep(0.001)
+        assert got is not None
+        assert srv.stats()["finished"] == 1
