@@ -127,6 +127,29 @@ def run_serving(cr, W, count: int, slots: int, precision: str) -> dict:
             "N_range": [int(min(r.x.shape[0] for r in reqs)), int(max(r.x.shape[0] for r in reqs))]}
 
 
+def run_large(cr, W, iters: int, precision: str) -> dict:
+    """K iterations of the N=40000, n=20 fit (the largest workload; 1.6e9 pairs)."""
+    name = "maxaff16_N40000_n20"
+    wl = W.WORKLOADS[name]
+    x, yb = W.make(name, seed=0)
+    with cr.Solver(x, yb, wl.delta, cr.Options(precision=precision)) as s:
+        t0 = time.perf_counter()
+        L, _, pit = s.lipschitz()
+        t1 = time.perf_counter()
+        s.iterate(iters)
+        t2 = time.perf_counter()
+        rep = s.report()
+    ms = rep["step_ms_low"] if precision != "fp64" else rep["step_ms_fp64"]
+    pairs = wl.N * (wl.N - 1)
+    gbs = PASS_BYTES[precision] * pairs / (ms * 1e-3) / 1e9 if ms > 0 else None
+    log(f"large fit: {iters} iterations in {t2 - t1:.2f} s, pass {ms:.3f} ms, {gbs:.0f} GB/s")
+    return {"workload": f"{name}: x~N(0,I_20), f0=max of 16 affine + 0.1||x||^2, eps~N(0,0.3^2), delta=1e-3",
+            "N": wl.N, "n": wl.n, "precision": precision, "iters": iters,
+            "dual_iters_per_s": round(iters / (t2 - t1), 1), "preprocess_s": round(t1 - t0, 3),
+            "power_iters": pit, "pass_ms": round(ms, 4), "pass_hbm_gbs": round(gbs, 1) if gbs else None,
+            "pass_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "kkt_after": rep["kkt"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +166,8 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=0, metavar="K",
                     help="also replay K requests of the serving stream (Poisson, 50/s) and report latency")
     ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
+    ap.add_argument("--large", type=int, default=300, metavar="K",
+                    help="also run K iterations of the N=40000, n=20 fit and report its pass rate (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -259,6 +284,8 @@ def main() -> int:
     }
     if args.serving > 0:
         out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision)
+    if args.large > 0:
+        out["large_fit"] = run_large(cr, W, args.large, args.precision)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations at N={wl.N} ...")
         out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters)

@@ -1,0 +1,119 @@
+"""Parity at the benchmark's full sizes.
+
+At N = 8000, n = 40 (the benchmark workload and launch configuration) the oracle cannot run a
+whole fit, but it can take one P-APG step from the GPU's own state: the test downloads
+lam^{k-1} and lam^{k-2}, lets the oracle form lam~^k, eta^k and lam^k, and compares sampled rows of
+the GPU's lam^k with it.  The FP64 stopping report is compared field by field at a 200-iteration
+point.  At N = 40000, n = 20 (the large-fit workload) the first step is checked on sampled rows
+(lam^1 = (-(ybar_j - ybar_i)/L)_+) and the rest through properties that hold at any size.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_02227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def quad8000():
+    return W.make("quad_N8000_n40", seed=0)
+
+
+def _a2_norm2(x):
+    """||A2||^2 = max_l lambda_max(sum_j (x_l - x_j)(x_l - x_j)^T) (A2 is block diagonal)."""
+    N = x.shape[0]
+    s = x.sum(axis=0)
+    G = x.T @ x
+    best = 0.0
+    for xl in x:
+        M = N * np.outer(xl, xl) - np.outer(xl, s) - np.outer(s, xl) + G
+        best = max(best, float(np.linalg.eigvalsh(M)[-1]))
+    return best
+
+
+def _oracle_step(x, ybar, delta, L, lam_km1, lam_km2, k):
+    """One P-APG step (Fig. fig:papg) from the stored iterates: returns lam^k."""
+    _, beta = oracle.fista_schedule(k)
+    b = beta[k - 1] if k >= 2 else 0.0
+    lt = lam_km1 + b * (lam_km1 - lam_km2)
+    y, xi = oracle.primal_from_dual(x, ybar, delta, lt)
+    s = oracle.pair_residual(x, y, xi)
+    lam = np.maximum(0.0, lt - s / L)
+    np.fill_diagonal(lam, 0.0)
+    return lam
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed_fp32", 1e-5)])
+def test_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
+    x, ybar = quad8000
+    delta = 1e-3
+    rows = np.random.default_rng(0).choice(8000, 48, replace=False)
+    with cr.Solver(x, ybar, delta, cr.Options(precision=precision)) as s:
+        L, s2, _ = s.lipschitz()
+        a2 = _a2_norm2(x)
+        assert a2 * (1 - 1e-6) <= s2 <= 2 * 8000 + a2          # Lemma lem:O1-constant
+        s.iterate(4)
+        lam4 = s.lam()
+        s.iterate(1)
+        lam5 = s.lam()
+        s.iterate(1)
+        got = np.vstack([s.lam_rows(int(r), 1) for r in rows])
+    ref = _oracle_step(x, ybar, delta, L, lam5, lam4, 6)[rows]
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.max(np.abs(got - ref)) <= rtol * scale
+    assert np.all(got >= 0.0)
+
+
+def test_report_parity_N8000(cr, torch_dev, quad8000):
+    x, ybar = quad8000
+    delta = 1e-3
+    with cr.Solver(x, ybar, delta) as s:
+        s.lipschitz()
+        s.iterate(200)
+        lam = s.lam()
+        rep = s.report()
+    ref = oracle.kkt_report(x, ybar, delta, lam)
+    for key in ["kkt", "nat_res_max", "max_viol", "infeas_rms", "dual_gap_paper"]:
+        assert rep[key] == pytest.approx(ref[key], rel=1e-9, abs=1e-15), key
+    for key in ["comp_sum", "primal_obj", "dual_obj"]:
+        assert rep[key] == pytest.approx(ref[key], rel=1e-9, abs=1e-12), key
+    cert = oracle.repair_certificate(x, ybar, delta, lam)
+    assert rep["cert_gap"] == pytest.approx(cert["cert_gap"], rel=1e-7)
+    assert rep["cert_gap"] >= 0.0
+
+
+def test_large_fit_N40000(cr, torch_dev):
+    x, ybar = W.make("maxaff16_N40000_n20", seed=0)
+    N = x.shape[0]
+    delta = 1e-3
+    rows = np.random.default_rng(1).choice(N, 16, replace=False)
+    with cr.Solver(x, ybar, delta, cr.Options(precision="mixed_fp32")) as s:
+        L, s2, _ = s.lipschitz()
+        assert 0.0 < s2 <= 2 * N + _a2_norm2(x)
+        s.iterate(1)
+        for r in rows:
+            got = s.lam_rows(int(r), 1)[0]
+            ref = np.maximum(0.0, -(ybar - ybar[r]) / L)
+            ref[r] = 0.0
+            assert np.max(np.abs(got - ref)) <= 1e-6 * max(1e-300, np.abs(ref).max())
+        s.iterate(199)
+        rep = s.report()
+    assert all(math.isfinite(rep[k]) for k in ["kkt", "primal_obj", "dual_obj", "cert_gap"])
+    assert rep["dual_obj"] > 0.0                      # g(0) = 0 and the ascent has made progress
+    assert rep["cert_gap"] >= 0.0                     # weak duality through the feasible repair
+    assert rep["dual_obj"] == pytest.approx(rep["primal_obj"] - rep["comp_sum"], rel=1e-12)
+    assert rep["iters"] == 200
+    assert rep["kkt"] < 1.0
