@@ -141,7 +141,8 @@ def fista_schedule(iters: int) -> tuple[np.ndarray, np.ndarray]:
 
 def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | None = None,
          max_iters: int = 100000, check_every: int = 50, lam0: np.ndarray | None = None,
-         momentum: bool = True, trace: list | None = None, iterates: list | None = None) -> dict:
+         momentum: bool = True, trace: list | None = None, iterates: list | None = None,
+         adaptive: bool = False, upsilon: float = 2.0, steps: list | None = None) -> dict:
     """Run P-APG (Fig. ``fig:papg``) from theta^0 = lam0 (default 0, as in Theorem ``bound``).
 
     Iteration k >= 1, with lam_tilde^1 = lam^0 and t_1 = 1:
@@ -150,7 +151,21 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
       3. t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
       4. lam_tilde^{k+1} = lam^k + (t_k - 1)/t_{k+1} (lam^k - lam^{k-1})
     ``momentum=False`` sets the extrapolation weight to zero, which is plain projected dual
-    gradient ascent (eq. ``eq:gd-rate``).  Every ``check_every`` iterations the stopping report
+    gradient ascent (eq. ``eq:gd-rate``).
+
+    ``adaptive=True`` replaces the constant step 1/L of Step 2 by the adaptive rule of Section 2.4
+    (the "PAPG_A" variant of Section 4): with s_0 = L and a factor upsilon > 1, iteration k uses
+    s_k = s_{k-1} * upsilon^(l_k - 1) for the smallest integer l_k >= 0 such that
+        g(lam^k) >= g(lam~^k) + <grad g(lam~^k), lam^k - lam~^k> - s_k/2 ||lam^k - lam~^k||^2
+    (eq. ``eq:adaptive-check``), lam^k being the Step-2 point computed with 1/s_k.  The paper does
+    not give upsilon; 2 is the default here.  ``steps``, when given, receives s_k for every k.
+    With every pair dualized g is exactly quadratic, g(lam) = -u^T ybar - ||u||^2/2 - ||w||^2/(2g)
+    for (u, w) = C^T lam, so for D = lam^k - lam~^k the check is the same statement as
+        ||A1^T D||^2 + ||A2^T D||^2 / g <= s_k ||D||^2,
+    which is how it is evaluated: the literal form subtracts dual values of size O(1) whose
+    difference near convergence is far below FP64 resolution.
+
+    Every ``check_every`` iterations the stopping report
     of ``kkt_report`` is evaluated at (lam^k, eta(lam^k)); the loop stops once its ``kkt`` is at
     most ``tol``.  ``iterates``, when given, receives (k, lam^k) for every k.
     """
@@ -164,11 +179,28 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
     rep = None
     k = 0
     status = "max_iters"
+    s_k = L
     for k in range(1, max_iters + 1):
         y, xi = primal_from_dual(x, ybar, gamma, lam_tilde)                    # step 1
         s = pair_residual(x, y, xi)
-        lam = np.maximum(0.0, lam_tilde - s / L)                               # step 2
-        np.fill_diagonal(lam, 0.0)
+        if not adaptive:
+            lam = np.maximum(0.0, lam_tilde - s / L)                           # step 2
+            np.fill_diagonal(lam, 0.0)
+        else:
+            ell = 0
+            while True:
+                s_try = s_k * upsilon ** (ell - 1)
+                lam = np.maximum(0.0, lam_tilde - s / s_try)                   # step 2, step 1/s_try
+                np.fill_diagonal(lam, 0.0)
+                dlt = lam - lam_tilde
+                du, dw = pair_adjoint(x, dlt)
+                curv = float(du @ du) + float(np.sum(dw * dw)) / gamma
+                if curv <= s_try * float(np.sum(dlt * dlt)) * (1.0 + 1e-12):
+                    break
+                ell += 1
+            s_k = s_try
+            if steps is not None:
+                steps.append(s_k)
         t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0                    # step 3
         beta = (t - 1.0) / t_next if momentum else 0.0
         lam_tilde = lam + beta * (lam - lam_prev)                              # step 4
@@ -188,7 +220,7 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
         rep = kkt_report(x, ybar, gamma, lam_prev)
     rep["k"] = k
     return {"y": y, "xi": xi, "lam": lam_prev, "L": L, "iters": k, "status": status,
-            "report": rep}
+            "report": rep, "step": s_k}
 
 
 # ---------------------------------------------------------------------------------------------

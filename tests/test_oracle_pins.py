@@ -375,3 +375,69 @@ def test_kkt_report_detects_violation():
     assert rep["nat_res_max"] == pytest.approx(rep["max_viol"], rel=1e-12)
     assert rep["infeas_rms"] > 0.0
     assert rep["scale"] == max(1.0, ybar.max() - ybar.min())
+
+
+# --- adaptive step (eq. eq:adaptive-check; PAPG_A of Section 4) --------------------------------
+
+def test_adaptive_check_is_the_quadratic_identity():
+    # With every pair dualized g is a concave quadratic, so g(lam~ + D) - g(lam~) - <grad g(lam~), D>
+    # equals -(||A1^T D||^2 + ||A2^T D||^2 / g) / 2 exactly: the paper's inequality is equivalent to
+    # ||A1^T D||^2 + ||A2^T D||^2 / g <= s ||D||^2.  Checked with explicit dual values.
+    x, ybar = W.sq_norm(25, 2, 0.1, 21)
+    gamma = 1e-2
+    rng = np.random.default_rng(4)
+    lt = rng.uniform(0, 0.01, (25, 25))
+    np.fill_diagonal(lt, 0.0)
+    D = rng.uniform(-0.002, 0.002, (25, 25))
+    np.fill_diagonal(D, 0.0)
+    y, xi = oracle.primal_from_dual(x, ybar, gamma, lt)
+    grad = -oracle.pair_residual(x, y, xi)
+    lhs = oracle.dual_objective(x, ybar, gamma, lt + D) - oracle.dual_objective(x, ybar, gamma, lt) \
+        - float(np.sum(grad * D))
+    u, w = oracle.pair_adjoint(x, D)
+    assert lhs == pytest.approx(-0.5 * (u @ u + np.sum(w * w) / gamma), rel=1e-8)
+
+
+@pytest.mark.parametrize("N,n,seed,gamma", [(12, 1, 0, 1e-1), (15, 2, 1, 1e-2), (10, 2, 3, 1e-3)])
+def test_adaptive_matches_exact_nnls(N, n, seed, gamma):
+    x, ybar = _rand_problem(N, n, seed)
+    ex = exact_solve(x, ybar, gamma)
+    steps = []
+    r = oracle.papg(x, ybar, gamma, 1e-11, max_iters=400000, check_every=50, adaptive=True, steps=steps)
+    assert r["status"] == "converged"
+    scale = max(1.0, np.abs(ex["y"]).max())
+    np.testing.assert_allclose(r["y"], ex["y"], rtol=0, atol=1e-8 * scale)
+    L, _, _ = oracle.lipschitz(x, gamma)
+    # the rule starts from s_0 = L and only multiplies by powers of upsilon
+    ratios = np.log2(np.array(steps) / L)
+    np.testing.assert_allclose(ratios, np.round(ratios), atol=1e-9)
+
+
+def test_adaptive_accepted_steps_satisfy_the_check_and_beat_constant_steps():
+    x, ybar = W.sq_norm(40, 2, 0.1, 6)
+    gamma = 1e-3
+    L, _, _ = oracle.lipschitz(x, gamma)
+    its, steps = [], []
+    oracle.papg(x, ybar, gamma, 0.0, L=L, max_iters=150, check_every=10 ** 9, adaptive=True,
+                iterates=its, steps=steps)
+    # re-derive every accepted step from the stored iterates and check eq. eq:adaptive-check
+    t, beta = oracle.fista_schedule(150)
+    prev = np.zeros((40, 40))
+    prev2 = np.zeros((40, 40))
+    for (k, lam), s in zip(its, steps):
+        b = beta[k - 1] if k >= 2 else 0.0
+        lt = prev + b * (prev - prev2)
+        y, xi = oracle.primal_from_dual(x, ybar, gamma, lt)
+        sres = oracle.pair_residual(x, y, xi)
+        ref = np.maximum(0.0, lt - sres / s)
+        np.fill_diagonal(ref, 0.0)
+        np.testing.assert_allclose(lam, ref, rtol=0, atol=1e-15)
+        d = lam - lt
+        gl = oracle.dual_objective(x, ybar, gamma, lam)
+        gt = oracle.dual_objective(x, ybar, gamma, lt)
+        assert gl >= gt - np.sum(sres * d) - 0.5 * s * np.sum(d * d) - 1e-12 * max(1.0, abs(gt))
+        prev2, prev = prev, lam
+    a = oracle.papg(x, ybar, gamma, 0.0, L=L, max_iters=150, check_every=150, adaptive=True)
+    c = oracle.papg(x, ybar, gamma, 0.0, L=L, max_iters=150, check_every=150)
+    assert a["report"]["dual_obj"] >= c["report"]["dual_obj"]
+    assert min(steps) < L
