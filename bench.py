@@ -2,8 +2,11 @@
 """Benchmark: dual-smoothing (P-APG) convex-regression fits on one MI355X.
 
 One step = one complete fit of the N=8000, n=40 quadratic-form workload to KKT residual 1e-4:
-Lipschitz preprocessing, P-APG iterations (one fused pair pass each), stopping tests every 50
-iterations, FP64 recovery of (y, xi) and the feasible-repair certificate.  Inputs are resident in
+Lipschitz preprocessing, P-APG iterations with the adaptive step of Section 2.4 (one fused trial
+pass each, two candidate steps per pass; a rejected pair costs another pass) and a gradient
+momentum restart (not part of the paper; ``--no-restart`` gives the paper's schedule), stopping
+tests every 50 iterations, FP64 recovery of (y, xi) and the feasible-repair certificate.
+``--step-rule constant`` runs the constant-step variant (step 1/L, one fused pass per iteration).  Inputs are resident in
 device memory before the timed region; outputs stay on the device.
 
 Prints one JSON line (stdout).  `value` is dual iterations per second over the timed fits
@@ -13,6 +16,7 @@ FP64 path on the same input, report the roofline of the fused pass, and time the
 oracle on the host cores on a bounded sample of the same fit.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed_fp32|mixed_bf16|fp64]
+                       [--step-rule adaptive|constant] [--no-restart] [--constant-compare] [--literal-compare]
 """
 from __future__ import annotations
 
@@ -42,27 +46,40 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-# Algorithmic HBM bytes per pair and per iteration of the fused pass, by precision mode:
-#   fp64       : read lam^{k-1}, lam^{k-2}, write lam^k, 8 bytes each            -> 24
-#   mixed_fp32 : read H (4), l^{k-1} (4), l^{k-2} (4), write l^k (4)              -> 16
-#   mixed_bf16 : read H (2), l^{k-1} (4), l^{k-2} (4), write l^k (4)              -> 14
-PASS_BYTES = {"fp64": 24, "mixed_fp32": 16, "mixed_bf16": 14}
-PASS_KERNEL = {"fp64": "pass_kernel<double,REP_F64,PASS_STEP,MB=3>",
-               "mixed_fp32": "pass_kernel<float,REP_SPLIT_F32,PASS_STEP,MB=3>",
-               "mixed_bf16": "pass_kernel<float,REP_SPLIT_BF16,PASS_STEP,MB=3>"}
+# Algorithmic HBM bytes per pair and per launch of the fused pass, by step rule and precision:
+# constant step (one pass per iteration)
+#   fp64       : read lam^{k-1}, lam^{k-2}, write lam^k, 8 bytes each                  -> 24
+#   mixed_fp32 : read H (4), l^{k-1} (4), l^{k-2} (4), write l^k (4)                    -> 16
+#   mixed_bf16 : read H (2), l^{k-1} (4), l^{k-2} (4), write l^k (4)                    -> 14
+# adaptive step (one trial pass per attempt: both iterates in, two candidates out)
+#   fp64       : read lam^k, lam^{k-1}, write two candidates, 8 bytes each             -> 32
+#   mixed_fp32 : read H (4), l^k (4), l^{k-1} (4), write two low-part candidates (8)   -> 20
+#   mixed_bf16 : read H (2), l^k (4), l^{k-1} (4), write two low-part candidates (8)   -> 18
+PASS_BYTES = {("constant", "fp64"): 24, ("constant", "mixed_fp32"): 16, ("constant", "mixed_bf16"): 14,
+              ("adaptive", "fp64"): 32, ("adaptive", "mixed_fp32"): 20, ("adaptive", "mixed_bf16"): 18}
+_REP = {"fp64": "double,REP_F64", "mixed_fp32": "float,REP_SPLIT_F32", "mixed_bf16": "float,REP_SPLIT_BF16"}
 
 
-def step_kernel_stats(rep: dict, precision: str) -> dict:
+def pass_kernel(rule: str, precision: str) -> str:
+    mode = "PASS_TRIAL" if rule == "adaptive" else "PASS_STEP"
+    return f"pass_kernel<{_REP[precision]},{mode},MB=3>"
+
+
+def step_kernel_stats(rep: dict, precision: str, rule: str) -> dict:
     """Dominant pass kernel of a fit (the phase with the larger total device time)."""
     low_iters = rep["iters_low"]
     hi_iters = rep["iters"] - rep["iters_low"]
+    # launches per accepted iteration: 1 for the constant step, trials / 2 / iters for the adaptive one
+    per_iter = (rep["trials"] / 2.0 / max(1, rep["iters"])) if rule == "adaptive" else 1.0
     t_low = low_iters * rep["step_ms_low"]
     t_hi = hi_iters * rep["step_ms_fp64"]
     if precision != "fp64" and t_low >= t_hi and rep["step_samples_low"] > 0:
-        return {"phase": "low", "ms": rep["step_ms_low"], "bytes_per_pair": PASS_BYTES[precision],
-                "launches": low_iters, "samples": rep["step_samples_low"], "kernel": PASS_KERNEL[precision]}
-    return {"phase": "fp64", "ms": rep["step_ms_fp64"], "bytes_per_pair": PASS_BYTES["fp64"], "launches": hi_iters,
-            "samples": rep["step_samples_fp64"], "kernel": PASS_KERNEL["fp64"]}
+        return {"phase": "low", "ms": rep["step_ms_low"], "bytes_per_pair": PASS_BYTES[(rule, precision)],
+                "launches": round(low_iters * per_iter), "samples": rep["step_samples_low"],
+                "kernel": pass_kernel(rule, precision)}
+    return {"phase": "fp64", "ms": rep["step_ms_fp64"], "bytes_per_pair": PASS_BYTES[(rule, "fp64")],
+            "launches": round(hi_iters * per_iter), "samples": rep["step_samples_fp64"],
+            "kernel": pass_kernel(rule, "fp64")}
 
 
 def traffic_for(kernel: str) -> dict | None:
@@ -76,7 +93,7 @@ def traffic_for(kernel: str) -> dict | None:
     return t.get("kernels", {}).get(kernel)
 
 
-def cpu_baseline(x, ybar, delta: float, L: float, iters: int) -> dict:
+def cpu_baseline(x, ybar, delta: float, L: float, iters: int, rule: str, restart: bool) -> dict:
     """The FP64 numpy oracle, untuned, on the host cores: `iters` P-APG iterations of the same fit."""
     import numpy as np
     import oracle
@@ -87,16 +104,19 @@ def cpu_baseline(x, ybar, delta: float, L: float, iters: int) -> dict:
     except Exception:
         pass
     t0 = time.perf_counter()
-    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=iters, check_every=10 ** 9)
+    steps = []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=iters, check_every=10 ** 9, adaptive=(rule == "adaptive"),
+                steps=steps, restart=restart)
     dt = time.perf_counter() - t0
     # the oracle's loop ends with one stopping report; charge it to the sample as well
     return {"value": iters / dt, "unit": "dual iterations/s", "cores": threads or os.cpu_count(),
             "kind": "oracle",
-            "sample": f"{iters} P-APG iterations (plus one stopping report) of the same N={x.shape[0]}, "
-                      f"n={x.shape[1]} fit in the FP64 numpy oracle, L fixed; {dt:.1f} s"}
+            "sample": f"the first {iters} P-APG iterations ({rule} step{', restart' if restart else ''}, plus one "
+                      f"stopping report) of the same "
+                      f"N={x.shape[0]}, n={x.shape[1]} fit in the FP64 numpy oracle, L fixed; {dt:.1f} s"}
 
 
-def run_serving(cr, W, count: int, slots: int, precision: str) -> dict:
+def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restart: bool) -> dict:
     """Replay a Poisson stream of fit requests through the continuous-batching context.
 
     Requests (N log-uniform in [100, 6000], n uniform in 2..32, ||x||^2 or 8-piece log-sum-exp,
@@ -105,7 +125,7 @@ def run_serving(cr, W, count: int, slots: int, precision: str) -> dict:
     """
     import numpy as np
     reqs = W.serving_requests(count=count, seed=0)
-    opt = cr.Options(precision=precision)
+    opt = cr.Options(precision=precision, step_rule=rule, restart=restart)
     ids = []
     with cr.Server(max_slots=slots) as srv:
         t0 = time.perf_counter()
@@ -120,19 +140,23 @@ def run_serving(cr, W, count: int, slots: int, precision: str) -> dict:
     iters = np.array([r.report["iters"] for r in res])
     conv = sum(1 for r in res if r.status == cr.CR_OK)
     log(f"serving: {count} fits in {t_end:.1f} s, p50 {np.percentile(lat, 50):.3f} s, p99 {np.percentile(lat, 99):.3f} s")
-    return {"requests": count, "slots": slots, "precision": precision, "wall_s": round(t_end, 3),
+    per = [[int(r.x.shape[0]), int(r.x.shape[1]), int(f.report["iters"]), round(float(f.extra["latency_s"]), 3),
+            round(float(f.report["seconds"]), 3)] for r, f in zip(reqs, res)]
+    return {"requests": count, "slots": slots, "precision": precision, "step_rule": rule, "restart": restart,
+            "wall_s": round(t_end, 3),
+            "per_request_N_n_iters_latency_fit_s": per,
             "fits_per_s": round(count / t_end, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "mean_iters": float(iters.mean()),
             "converged": conv, "arrival_span_s": round(reqs[-1].arrival_s, 3),
             "N_range": [int(min(r.x.shape[0] for r in reqs)), int(max(r.x.shape[0] for r in reqs))]}
 
 
-def run_large(cr, W, iters: int, precision: str) -> dict:
+def run_large(cr, W, iters: int, precision: str, rule: str, restart: bool) -> dict:
     """K iterations of the N=40000, n=20 fit (the largest workload; 1.6e9 pairs)."""
     name = "maxaff16_N40000_n20"
     wl = W.WORKLOADS[name]
     x, yb = W.make(name, seed=0)
-    with cr.Solver(x, yb, wl.delta, cr.Options(precision=precision)) as s:
+    with cr.Solver(x, yb, wl.delta, cr.Options(precision=precision, step_rule=rule, restart=restart)) as s:
         t0 = time.perf_counter()
         L, _, pit = s.lipschitz()
         t1 = time.perf_counter()
@@ -141,10 +165,11 @@ def run_large(cr, W, iters: int, precision: str) -> dict:
         rep = s.report()
     ms = rep["step_ms_low"] if precision != "fp64" else rep["step_ms_fp64"]
     pairs = wl.N * (wl.N - 1)
-    gbs = PASS_BYTES[precision] * pairs / (ms * 1e-3) / 1e9 if ms > 0 else None
+    gbs = PASS_BYTES[(rule, precision)] * pairs / (ms * 1e-3) / 1e9 if ms > 0 else None
     log(f"large fit: {iters} iterations in {t2 - t1:.2f} s, pass {ms:.3f} ms, {gbs:.0f} GB/s")
     return {"workload": f"{name}: x~N(0,I_20), f0=max of 16 affine + 0.1||x||^2, eps~N(0,0.3^2), delta=1e-3",
-            "N": wl.N, "n": wl.n, "precision": precision, "iters": iters,
+            "N": wl.N, "n": wl.n, "precision": precision, "step_rule": rule, "restart": restart, "iters": iters,
+            "trial_passes": int(rep["trials"] / 2) if rule == "adaptive" else iters,
             "dual_iters_per_s": round(iters / (t2 - t1), 1), "preprocess_s": round(t1 - t0, 3),
             "power_iters": pit, "pass_ms": round(ms, 4), "pass_hbm_gbs": round(gbs, 1) if gbs else None,
             "pass_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "kkt_after": rep["kkt"]}
@@ -156,6 +181,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "mixed_bf16", "fp64"])
+    ap.add_argument("--step-rule", default="adaptive", choices=["adaptive", "constant"],
+                    help="adaptive step of Section 2.4 (default) or the constant step 1/L")
+    ap.add_argument("--no-restart", action="store_true",
+                    help="adaptive step without the momentum restart (the paper's schedule)")
+    ap.add_argument("--constant-compare", action="store_true",
+                    help="also time one constant-step fit at the same precision")
+    ap.add_argument("--literal-compare", type=int, default=0, metavar="K",
+                    help="also run the adaptive step without restart for at most K iterations")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison fit")
@@ -191,11 +224,14 @@ def main() -> int:
     yb = torch.from_numpy(yb_h).to(dev)
     torch.cuda.synchronize()
 
-    def one_fit(precision: str):
-        opt = cr.Options(precision=precision, device=0,
+    rule = args.step_rule
+    restart = rule == "adaptive" and not args.no_restart
+
+    def one_fit(precision: str, step_rule: str = rule, rst: bool = restart, max_iters: int = args.max_iters):
+        opt = cr.Options(precision=precision, device=0, step_rule=step_rule, restart=rst,
                          stream=torch.cuda.current_stream(dev).cuda_stream)
-        if args.max_iters > 0:
-            opt.max_iters = args.max_iters
+        if max_iters > 0:
+            opt.max_iters = max_iters
         return cr.fit(x, yb, wl.delta, args.tol, opt)
 
     for w in range(args.warmup):
@@ -217,7 +253,7 @@ def main() -> int:
     iters_total = sum(r["iters"] for r in reps)
     value = iters_total / elapsed
     last = reps[-1]
-    ks = step_kernel_stats(last, args.precision)
+    ks = step_kernel_stats(last, args.precision, rule)
     pairs = wl.N * (wl.N - 1)
     alg_bytes = ks["bytes_per_pair"] * pairs
     achieved = alg_bytes / (ks["ms"] * 1e-3) / 1e9 if ks["ms"] > 0 else 0.0
@@ -226,13 +262,18 @@ def main() -> int:
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "kernel": ks["kernel"], "avg_launch_ms": round(ks["ms"], 5), "sampled_launches": int(ks["samples"]),
-                "algorithmic_bytes_per_launch": alg_bytes,
-                "mfma_tflops": round(4.0 * pairs * wl.n / (ks["ms"] * 1e-3) / 1e12, 2) if ks["ms"] > 0 else 0.0}
+                "algorithmic_bytes_per_launch": alg_bytes, "launches_per_fit": ks["launches"],
+                # residual + adjoint contractions (2 flops per multiply-add each), twice for the trial pass
+                "mfma_tflops": round((6.0 if rule == "adaptive" else 4.0) * pairs * wl.n / (ks["ms"] * 1e-3) / 1e12, 2)
+                if ks["ms"] > 0 else 0.0}
 
     extra = {
         "time_to_tol_s": [round(r["seconds"], 4) for r in reps],
         "iters": [r["iters"] for r in reps],
         "iters_low_precision": [r["iters_low"] for r in reps],
+        "trial_passes": [int(r["trials"] / 2) for r in reps] if rule == "adaptive" else None,
+        "restarts": [int(r["restarts"]) for r in reps],
+        "step_final_over_L": last["step_final"] / last["L"],
         "kkt_final": last["kkt"],
         "max_viol_final": last["max_viol"],
         "preprocess_s": round(last["preprocess_seconds"], 4),
@@ -250,21 +291,44 @@ def main() -> int:
         rep64 = r64.report
         ymix = results[-1].y.cpu().numpy()
         y64 = r64.y.cpu().numpy()
-        ks64 = step_kernel_stats(rep64, "fp64")
+        ks64 = step_kernel_stats(rep64, "fp64", rule)
         extra.update({
             "fp64_time_to_tol_s": round(dt64, 4),
             "fp64_iters": rep64["iters"],
             "fp64_dual_iters_per_s": round(rep64["iters"] / dt64, 1),
             "fp64_kkt_final": rep64["kkt"],
-            "fp64_step_hbm_gbs": round(24 * pairs / (ks64["ms"] * 1e-3) / 1e9, 1) if ks64["ms"] > 0 else None,
+            "fp64_step_hbm_gbs": round(PASS_BYTES[(rule, "fp64")] * pairs / (ks64["ms"] * 1e-3) / 1e9, 1)
+            if ks64["ms"] > 0 else None,
             "mixed_vs_fp64_speedup": round(dt64 / (elapsed / args.steps), 3),
             "mixed_vs_fp64_y_maxabs": float(np.max(np.abs(ymix - y64))),
             "mixed_vs_fp64_y_rel": float(np.max(np.abs(ymix - y64)) / np.max(np.abs(y64))),
         })
         log(f"fp64 comparison: {rep64['iters']} iters in {dt64:.2f} s")
 
+    if args.constant_compare and rule == "adaptive":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc_ = one_fit(args.precision, "constant", False)
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t1
+        extra.update({"constant_step_time_to_tol_s": round(dtc, 4), "constant_step_iters": rc_.report["iters"],
+                      "adaptive_vs_constant_speedup": round(dtc / (elapsed / args.steps), 3)})
+        log(f"constant-step comparison: {rc_.report['iters']} iters in {dtc:.2f} s")
+
+    if args.literal_compare > 0 and rule == "adaptive":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rl = one_fit(args.precision, "adaptive", False, args.literal_compare)
+        torch.cuda.synchronize()
+        dtl = time.perf_counter() - t1
+        extra.update({"no_restart_status": rl.status, "no_restart_iters": rl.report["iters"],
+                      "no_restart_kkt": rl.report["kkt"], "no_restart_s": round(dtl, 4)})
+        log(f"adaptive step without restart: status {rl.status}, {rl.report['iters']} iters, "
+            f"kkt {rl.report['kkt']:.3e}, {dtl:.2f} s")
+
     out = {
         "metric": "dual P-APG iterations/s and time-to-1e-4 KKT, N=8000 n=40 convex-regression fit",
+        # value: accepted iterations per second of whole-fit wall time; ms_per_step: time-to-tolerance
         "value": round(value, 1),
         "unit": "dual iterations/s",
         "n_gpus": 1,
@@ -279,16 +343,17 @@ def main() -> int:
         "config": {"workload": f"{WORKLOAD}: x~U[-1,1]^40, f0=x^T Q x with Q=M^T M/40, eps~N(0,0.5^2), "
                                f"delta=1e-3, KKT tol {args.tol:g}",
                    "N": wl.N, "n": wl.n, "delta": wl.delta, "tol": args.tol, "precision": args.precision,
+                   "step_rule": rule, "momentum_restart": restart,
                    "seed": args.seed},
         "roofline": roofline,
     }
     if args.serving > 0:
-        out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision)
+        out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision, rule, restart)
     if args.large > 0:
-        out["large_fit"] = run_large(cr, W, args.large, args.precision)
+        out["large_fit"] = run_large(cr, W, args.large, args.precision, rule, restart)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations at N={wl.N} ...")
-        out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters, rule, restart)
     out.update(extra)
     print(json.dumps(out), flush=True)
     return 0

@@ -70,7 +70,16 @@ typedef struct {
     void *stream;            /* hipStream_t to run on; NULL: the library's own stream */
     int32_t stall_checks;    /* mixed modes: switch to FP64 after this many consecutive stopping
                                 tests without a new lowest KKT residual; default 100 */
-    int32_t reserved[7];
+    int32_t step_rule;       /* 1 (default): adaptive step of the paper's eq. "eq:adaptive-check"
+                                (PAPG_A) with s_0 = L and s_k = s_{k-1} upsilon^(l_k - 1);
+                                0: constant step 1/L (PAPG_C) */
+    double upsilon;          /* adaptive step factor (> 1); default 2 */
+    int32_t restart;         /* adaptive step only. 1: reset the momentum (t := 1) after an iteration
+                                whose accepted step opposes its own movement,
+                                <lam^{k+1} - lam~^{k+1}, lam^{k+1} - lam^k> < 0 (gradient restart
+                                of O'Donoghue and Candes); 0: the paper's schedule unchanged.
+                                Default 1 */
+    int32_t reserved[3];
 } cr_options;
 
 typedef struct {
@@ -111,7 +120,11 @@ typedef struct {
     double step_ms_fp64;
     double step_samples_low;
     double step_samples_fp64;
-    double reserved[2];
+    /* Adaptive step: the last accepted s_k (L for the constant step) and the number of Step-2
+       candidates evaluated (two per fused trial pass). */
+    double step_final;
+    double trials;
+    double restarts;         /* momentum restarts taken (options.restart) */
 } cr_report;
 
 /* Fills *opt with the defaults listed above. */
@@ -164,7 +177,8 @@ int cr_solver_lipschitz(cr_solver *s, double *L, double *sigma2, int32_t *iters)
 /* Uses the given L (> 0) instead. */
 int cr_solver_set_L(cr_solver *s, double L);
 
-/* Advances the P-APG iteration `iters` times in the solver's current precision. */
+/* Advances the P-APG iteration `iters` times (accepted iterations under the adaptive rule) in the
+ * solver's current precision. */
 int cr_solver_iterate(cr_solver *s, int64_t iters);
 
 /* Runs iterations with stopping tests until report.kkt <= tol or a budget ends (cr_fit's loop).

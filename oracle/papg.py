@@ -142,7 +142,8 @@ def fista_schedule(iters: int) -> tuple[np.ndarray, np.ndarray]:
 def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | None = None,
          max_iters: int = 100000, check_every: int = 50, lam0: np.ndarray | None = None,
          momentum: bool = True, trace: list | None = None, iterates: list | None = None,
-         adaptive: bool = False, upsilon: float = 2.0, steps: list | None = None) -> dict:
+         adaptive: bool = False, upsilon: float = 2.0, steps: list | None = None,
+         restart: bool = False) -> dict:
     """Run P-APG (Fig. ``fig:papg``) from theta^0 = lam0 (default 0, as in Theorem ``bound``).
 
     Iteration k >= 1, with lam_tilde^1 = lam^0 and t_1 = 1:
@@ -164,6 +165,11 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
         ||A1^T D||^2 + ||A2^T D||^2 / g <= s_k ||D||^2,
     which is how it is evaluated: the literal form subtracts dual values of size O(1) whose
     difference near convergence is far below FP64 resolution.
+
+    ``restart=True`` (adaptive step only; not part of the paper) resets the momentum, t := 1, after
+    an iteration whose accepted step opposes the iterate's movement,
+    <lam^k - lam~^k, lam^k - lam^{k-1}> < 0 (the gradient restart of O'Donoghue and Candes,
+    "Adaptive restart for accelerated gradient schemes", 2015), so that lam~^{k+1} = lam^k.
 
     Every ``check_every`` iterations the stopping report
     of ``kkt_report`` is evaluated at (lam^k, eta(lam^k)); the loop stops once its ``kkt`` is at
@@ -201,6 +207,8 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
             s_k = s_try
             if steps is not None:
                 steps.append(s_k)
+            if restart and float(np.sum(dlt * (lam - lam_prev))) < 0.0:
+                t = 1.0
         t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0                    # step 3
         beta = (t - 1.0) / t_next if momentum else 0.0
         lam_tilde = lam + beta * (lam - lam_prev)                              # step 4

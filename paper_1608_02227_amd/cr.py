@@ -35,7 +35,10 @@ class CROptions(C.Structure):
         ("device", C.c_int32),
         ("stream", C.c_void_p),
         ("stall_checks", C.c_int32),
-        ("reserved", C.c_int32 * 7),
+        ("step_rule", C.c_int32),
+        ("upsilon", C.c_double),
+        ("restart", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -69,11 +72,14 @@ class CRReport(C.Structure):
         ("step_ms_fp64", C.c_double),
         ("step_samples_low", C.c_double),
         ("step_samples_fp64", C.c_double),
-        ("reserved", C.c_double * 2),
+        ("step_final", C.c_double),
+        ("trials", C.c_double),
+        ("restarts", C.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
 
 
 class CRError(RuntimeError):
@@ -169,6 +175,9 @@ class Options:
     device: int = 0
     stream: int | None = None
     stall_checks: int = 100
+    step_rule: str = "adaptive"     # "adaptive" (PAPG_A) or "constant" (PAPG_C, step 1/L)
+    upsilon: float = 2.0
+    restart: bool = True            # adaptive step: gradient momentum restart (not in the paper)
 
     def to_c(self) -> CROptions:
         o = CROptions()
@@ -185,6 +194,9 @@ class Options:
         o.device = self.device
         o.stream = self.stream
         o.stall_checks = self.stall_checks
+        o.step_rule = {"constant": 0, "adaptive": 1}[self.step_rule]
+        o.upsilon = self.upsilon
+        o.restart = 1 if self.restart else 0
         return o
 
 

@@ -24,8 +24,12 @@ LamRep rep_of(int precision) {
     return precision == CR_FP64 ? REP_F64 : (precision == CR_MIXED_FP32 ? REP_SPLIT_F32 : REP_SPLIT_BF16);
 }
 
-// bytes of the two-iterate multiplier state per (padded) pair
-size_t state_bytes_per_pair(LamRep r) { return r == REP_F64 ? 16 : (r == REP_SPLIT_F32 ? 12 : 10); }
+// bytes of the multiplier state per (padded) pair: two iterates plus, for the adaptive step, two
+// candidate buffers (the split forms add the shared high part)
+size_t state_bytes_per_pair(LamRep r, bool adaptive) {
+    const size_t iterates = adaptive ? 4 : 2;
+    return r == REP_F64 ? 8 * iterates : 4 * iterates + (r == REP_SPLIT_F32 ? 4 : 2);
+}
 
 bool all_finite(const double *p, size_t n) {
     for (size_t i = 0; i < n; ++i)
@@ -61,6 +65,9 @@ extern "C" void cr_default_options(cr_options *opt) {
     opt->device = 0;
     opt->stream = nullptr;
     opt->stall_checks = 100;
+    opt->step_rule = 1;
+    opt->upsilon = 2.0;
+    opt->restart = 1;
 }
 
 extern "C" const char *cr_strerror(int code) {
@@ -122,11 +129,11 @@ cr_solver::~cr_solver() {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
-size_t cr_state_bytes(int64_t N, int64_t n, int precision) {
+size_t cr_state_bytes(int64_t N, int64_t n, int precision, bool adaptive) {
     Geometry g = make_geometry((int)N, (int)n);
-    size_t b = (size_t)g.Nr * g.ld * state_bytes_per_pair(rep_of(precision));
-    b += (size_t)g.chunks * g.Nr * g.NP * 8 + (size_t)g.strips * g.ld * 12;
-    b += (size_t)g.Nr * g.NP * 8 * 6 + (size_t)g.Nr * 8 * 16;
+    size_t b = (size_t)g.Nr * g.ld * state_bytes_per_pair(rep_of(precision), adaptive);
+    b += (size_t)g.chunks * g.Nr * g.NP * 8 * (adaptive ? 2 : 1) + (size_t)g.strips * g.ld * 12 * (adaptive ? 2 : 1);
+    b += (size_t)g.Nr * g.NP * 8 * (adaptive ? 12 : 6) + (size_t)g.Nr * 8 * 24;
     return b;
 }
 
@@ -138,6 +145,9 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->precision < CR_FP64 || opt->precision > CR_MIXED_BF16) return CR_EINVAL;
         if (opt->check_every < 1 || opt->max_iters < 0 || opt->power_max_iters < 1) return CR_EINVAL;
         if (opt->L < 0.0 || !std::isfinite(opt->L) || opt->time_budget_s < 0.0) return CR_EINVAL;
+        if (opt->step_rule < 0 || opt->step_rule > 1) return CR_EINVAL;
+        if (opt->step_rule == 1 && !(opt->upsilon > 1.0 && std::isfinite(opt->upsilon))) return CR_EINVAL;
+        if (opt->restart < 0 || opt->restart > 1) return CR_EINVAL;
     }
     return CR_OK;
 }
@@ -179,6 +189,8 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     }
     s->precision = opt.precision;
     s->rep = rep_of(opt.precision);
+    s->adaptive = opt.step_rule == 1;
+    s->upsilon = opt.upsilon;
     s->fp32pass = opt.precision != CR_FP64;
     double ymin = hy[0], ymax = hy[0];
     for (double v : hy) { ymin = std::min(ymin, v); ymax = std::max(ymax, v); }
@@ -203,6 +215,10 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
 #define CR_ALLOC(ptr, bytes) do { int r_ = s->alloc((void **)&(ptr), (bytes)); if (r_) return bail(r_); } while (0)
     CR_ALLOC(s->lam[0], lamsz);
     CR_ALLOC(s->lam[1], lamsz);
+    if (s->adaptive) {
+        CR_ALLOC(s->lam[2], lamsz);
+        CR_ALLOC(s->lam[3], lamsz);
+    }
     if (s->rep != REP_F64) {
         CR_ALLOC(s->lam_hi, pairs_p * (s->rep == REP_SPLIT_F32 ? 4 : 2));
         CR_ALLOC(s->ubase, nr * 8);
@@ -226,6 +242,17 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     CR_ALLOC(s->part_min, (size_t)g.strips * g.ld * 8);
     CR_ALLOC(s->part_arg, (size_t)g.strips * g.ld * 4);
     CR_ALLOC(s->scal, 32 * 8);
+    if (s->adaptive) {
+        CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
+        CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
+        for (int q = 0; q < 2; ++q) {
+            CR_ALLOC(s->uD[q], nr * 8);
+            CR_ALLOC(s->wD[q], rows_np * 8);
+            CR_ALLOC(s->ye[q], nr * 8);
+            CR_ALLOC(s->xie[q], rows_np * 8);
+            CR_ALLOC(s->dmye[q], nr * 8);
+        }
+    }
     if (s->fp32pass) {
         CR_ALLOC(s->xhat32, rows_np * 4);
         CR_ALLOC(s->y32, nr * 4);
@@ -280,6 +307,10 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     }
     H(hipMemsetAsync(s->part_acc, 0, (size_t)g.chunks * rows_np * 8, s->stream));
     H(hipMemsetAsync(s->part_col, 0, (size_t)g.strips * g.ld * 8, s->stream));
+    if (s->adaptive) {
+        H(hipMemsetAsync(s->part_acc2, 0, (size_t)g.chunks * rows_np * 8, s->stream));
+        H(hipMemsetAsync(s->part_col2, 0, (size_t)g.strips * g.ld * 8, s->stream));
+    }
     H(hipStreamSynchronize(s->stream));
     s->release(dx);
     s->release(dyb);
@@ -332,7 +363,7 @@ int cr_solver::rebase() {
     PassArgs a{};
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
-    a.lam_b = lam[1 - cur];
+    a.lam_b = lam[prv];
     a.xhat = xhat64;
     a.part_acc = part_acc;
     a.part_col = part_col;
@@ -354,6 +385,12 @@ int cr_solver::rebase() {
 int cr_solver::prime() {
     int rc = rebase();
     if (rc) return rc;
+    if (adaptive) {
+        rc = refresh_eta(false);
+        if (rc) return rc;
+        primed = true;
+        return CR_OK;
+    }
     // lam~^{k+1} = lam^k + beta_k (lam^k - lam^{k-1}) is linear in the stored iterates, so its
     // adjoint is (1 + beta) C^T lam^k - beta C^T lam^{k-1}; at k = 0 (or beta = 0) only lam^k counts.
     if (k == 0 || beta_last == 0.0) {
@@ -362,12 +399,133 @@ int cr_solver::prime() {
     } else {
         rc = adjoint_to(cur, yc, xic, dmyc, false, nullptr, nullptr, nullptr);
         if (rc) return rc;
-        rc = adjoint_to(1 - cur, yr, xir, dmyr, false, nullptr, nullptr, nullptr);
+        rc = adjoint_to(prv, yr, xir, dmyr, false, nullptr, nullptr, nullptr);
         if (rc) return rc;
-        CR_HIP(launch_combine(g, yc, xic, yr, xir, ybar64, xhat64, beta_last, y64, xi64, dmy64, y32, xi32, dmy32,
-                              stream));
+        const double b = beta_last;
+        CR_HIP(launch_lincomb(g, yc, xic, yr, xir, 1.0 + b, -b, 1.0 + b, -b, xhat64, y64, xi64, dmy64, y32, xi32,
+                              dmy32, stream));
     }
     primed = true;
+    return CR_OK;
+}
+
+// Adaptive step: recompute eta(lam^k) and eta(lam^{k-1}) exactly in FP64 from the stored
+// iterates (the running updates between stopping tests add FP32-accurate increments) and the
+// next extrapolated point eta(lam~^{k+1}) from them.  have_cur_in_yc: eta(lam^k) is already in
+// yc / xic / dmyc (fresh from a stopping test).
+int cr_solver::refresh_eta(bool have_cur_in_yc) {
+    const size_t nr = g.Nr, rows_np = (size_t)g.Nr * g.NP;
+    if (have_cur_in_yc) {
+        CR_HIP(hipMemcpyAsync(ye[ecur], yc, nr * 8, hipMemcpyDeviceToDevice, stream));
+        CR_HIP(hipMemcpyAsync(xie[ecur], xic, rows_np * 8, hipMemcpyDeviceToDevice, stream));
+        CR_HIP(hipMemcpyAsync(dmye[ecur], dmyc, nr * 8, hipMemcpyDeviceToDevice, stream));
+    } else {
+        int rc = adjoint_to(cur, ye[ecur], xie[ecur], dmye[ecur], false, nullptr, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    int rc = adjoint_to(prv, ye[1 - ecur], xie[1 - ecur], dmye[1 - ecur], false, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    const double b = opt.momentum ? beta_last : 0.0;
+    CR_HIP(launch_lincomb(g, ye[ecur], xie[ecur], ye[1 - ecur], xie[1 - ecur], 1.0 + b, -b, 1.0 + b, -b, xhat64, y64,
+                          xi64, dmy64, fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr, fp32pass ? dmy32 : nullptr,
+                          stream));
+    return CR_OK;
+}
+
+// One iteration under the adaptive rule of eq. "eq:adaptive-check" (s_0 = L, s_k = s_{k-1}
+// upsilon^(l_k - 1), smallest admissible l_k >= 0).  Each fused trial pass evaluates two consecutive
+// candidates l and l + 1 from one read of the iterates.  With every pair dualized the dual function
+// is exactly quadratic, so the check for D = lam^k - lam~^k reads
+//     ||A1^T D||^2 + ||A2^T D||^2 / delta <= s ||D||^2,
+// which the pass provides directly (adjoint of D and ||D||^2) without differencing dual values.
+int cr_solver::step_adaptive() {
+    if (!primed) {
+        int rc = prime();
+        if (rc) return rc;
+    }
+    const double bk = opt.momentum ? beta_last : 0.0;   // forms lam~^{k+1} from lam^k, lam^{k-1}
+    double sa = s_step / upsilon, sb = s_step;
+    int accepted = -1;
+    double s_new = s_step;
+    bool restart_now = false;
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        PassArgs a{};
+        a.lam_h = lam_hi;
+        a.lam_a = lam[cur];
+        a.lam_b = lam[prv];
+        a.lam_c = lam[fa];
+        a.lam_d = lam[fb];
+        a.beta_prev = bk;
+        a.inv_L = 1.0 / sa;
+        a.inv_L2 = 1.0 / sb;
+        a.part_acc = part_acc;
+        a.part_col = part_col;
+        a.part_acc2 = part_acc2;
+        a.part_col2 = part_col2;
+        a.part_red = part_red;
+        if (fp32pass) {
+            a.xhat = xhat32; a.xi = xi32; a.yv = y32; a.dmy = dmy32;
+        } else {
+            a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
+        }
+        const bool timed = !ev_pending;
+        if (timed) CR_HIP(hipEventRecord(ev_a, stream));
+        CR_HIP(launch_pass(g, PASS_TRIAL, fp32pass, rep, a, stream));
+        if (timed) {
+            CR_HIP(hipEventRecord(ev_b, stream));
+            ev_pending = true;
+            ev_pending_low = fp32pass;
+        }
+        for (int q = 0; q < 2; ++q) {
+            FinalizeArgs f{};
+            f.part_acc = q ? part_acc2 : part_acc;
+            f.part_col = q ? part_col2 : part_col;
+            f.xf = xhat64;
+            f.ybar = ybar64;
+            f.y = uD[q]; f.xi = wD[q]; f.dmy = dmyr;
+            f.rowred = rowred;
+            f.inv_delta = 1.0;
+            f.power = 1;
+            CR_HIP(launch_finalize(g, fp32pass, f, stream));
+            CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 2 * q, stream));
+        }
+        CR_HIP(launch_reduce(part_red, g.grid(), kRed, 0, 4, scal + 4, stream));
+        CR_HIP(hipMemcpyAsync(h_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        CR_HIP(hipStreamSynchronize(stream));
+        collect_timing();
+        trials += 2.0;
+        for (int q = 0; q < 8; ++q)
+            if (!std::isfinite(h_scal[q])) return CR_ENUMERIC;
+        const double curv_a = h_scal[0] + h_scal[1] / delta, curv_b = h_scal[2] + h_scal[3] / delta;
+        if (curv_a <= sa * h_scal[4] * (1.0 + 1e-12)) { accepted = 0; s_new = sa; restart_now = h_scal[6] < 0.0; break; }
+        if (curv_b <= sb * h_scal[5] * (1.0 + 1e-12)) { accepted = 1; s_new = sb; restart_now = h_scal[7] < 0.0; break; }
+        sa = sb * upsilon;
+        sb = sa * upsilon;
+    }
+    if (accepted < 0) return CR_ENUMERIC;   // no admissible step after 2^128-fold growth
+    // eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta), into the slot of eta(lam^{k-1})
+    const int en = 1 - ecur;
+    CR_HIP(launch_lincomb(g, y64, xi64, uD[accepted], wD[accepted], 1.0, 1.0, 1.0, 1.0 / delta, xhat64, ye[en],
+                          xie[en], dmye[en], nullptr, nullptr, nullptr, stream));
+    ecur = en;
+    const int c = cur, p = prv, A = fa, B = fb;
+    if (accepted == 0) { cur = A; prv = c; fa = p; fb = B; }
+    else { cur = B; prv = c; fa = A; fb = p; }
+    // optional gradient restart: the accepted step points against the iterate's own movement
+    if (opt.restart && restart_now) {
+        t = 1.0;
+        restarts += 1.0;
+    }
+    const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
+    CR_HIP(launch_lincomb(g, ye[ecur], xie[ecur], ye[1 - ecur], xie[1 - ecur], 1.0 + beta_k, -beta_k, 1.0 + beta_k,
+                          -beta_k, xhat64, y64, xi64, dmy64, fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr,
+                          fp32pass ? dmy32 : nullptr, stream));
+    t = t_next;
+    beta_last = beta_k;
+    s_step = s_new;
+    ++k;
+    if (fp32pass) ++k_low;
     return CR_OK;
 }
 
@@ -381,7 +539,7 @@ int cr_solver::step_once() {
     PassArgs a{};
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
-    a.lam_b = lam[1 - cur];
+    a.lam_b = lam[prv];
     a.beta_prev = opt.momentum ? beta_last : 0.0;
     a.beta_next = beta_k;
     a.inv_L = 1.0 / L;
@@ -413,7 +571,7 @@ int cr_solver::step_once() {
     f.wbase = wbase;
     f.inv_delta = 1.0 / delta;
     CR_HIP(launch_finalize(g, fp32pass, f, stream));
-    cur = 1 - cur;
+    std::swap(cur, prv);
     t = t_next;
     beta_last = beta_k;
     ++k;
@@ -464,6 +622,7 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
     sigma2 = est;
     L = est / delta;
     if (!(L > 0.0)) L = 1.0 / delta;   // every x equal and N = 1: any positive step is exact
+    s_step = L;
     power_iters = it;
     preprocess_s = now_s() - t0;
     primed = false;
@@ -529,6 +688,9 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
     rep_out->step_samples_low = step_n[0];
     rep_out->step_samples_fp64 = step_n[1];
     rep_out->step_ms_low = step_n[0] > 0 ? step_ms_sum[0] / step_n[0] : 0.0;
+    rep_out->step_final = adaptive ? s_step : L;
+    rep_out->trials = trials;
+    rep_out->restarts = restarts;
     rep_out->step_ms_fp64 = step_n[1] > 0 ? step_ms_sum[1] / step_n[1] : 0.0;
     bool finite = true;
     for (int q = 0; q < nsc; ++q) finite = finite && std::isfinite(h_scal[q]);
@@ -541,21 +703,24 @@ int cr_solver::promote() {
     if (rep == REP_F64) return CR_OK;
     CR_HIP(hipSetDevice(device));
     const size_t bytes = (size_t)g.Nr * g.ld * 8;
-    void *n0 = nullptr, *n1 = nullptr;
-    int rc = alloc(&n0, bytes);
-    if (rc) return rc;
-    rc = alloc(&n1, bytes);
-    if (rc) { release(n0); return rc; }
-    CR_HIP(launch_merge(g, rep, lam_hi, (const float *)lam[0], (double *)n0, stream));
-    CR_HIP(launch_merge(g, rep, lam_hi, (const float *)lam[1], (double *)n1, stream));
+    const int nbuf = adaptive ? 4 : 2;
+    void *nb[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int q = 0; q < nbuf; ++q) {
+        int rc = alloc(&nb[q], bytes);
+        if (rc) {
+            for (int p = 0; p < q; ++p) release(nb[p]);
+            return rc;
+        }
+    }
+    CR_HIP(launch_merge(g, rep, lam_hi, (const float *)lam[cur], (double *)nb[0], stream));
+    CR_HIP(launch_merge(g, rep, lam_hi, (const float *)lam[prv], (double *)nb[1], stream));
     CR_HIP(hipStreamSynchronize(stream));
-    release(lam[0]);
-    release(lam[1]);
+    for (int q = 0; q < 4; ++q) release(lam[q]);
     release(lam_hi);
     release(ubase);
     release(wbase);
-    lam[0] = n0;
-    lam[1] = n1;
+    for (int q = 0; q < 4; ++q) lam[q] = nb[q];
+    cur = 0; prv = 1; fa = 2; fb = 3;
     lam_hi = nullptr;
     ubase = nullptr;
     wbase = nullptr;
@@ -586,9 +751,9 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
         int rc = check(&rep, false);
         ++checks;
         if (trace)
-            fprintf(stderr, "cr trace: k=%lld kkt=%.4e viol=%.4e infeas=%.4e dual=%.12e low=%d t=%.3f\n",
-                    (long long)k, rep.kkt, rep.max_viol, rep.infeas_rms, rep.dual_obj, fp32pass ? 1 : 0,
-                    now_s() - t0);
+            fprintf(stderr, "cr trace: k=%lld kkt=%.4e viol=%.4e infeas=%.4e dual=%.12e low=%d s/L=%.3e trials=%.0f "
+                    "t=%.3f\n", (long long)k, rep.kkt, rep.max_viol, rep.infeas_rms, rep.dual_obj, fp32pass ? 1 : 0,
+                    adaptive ? s_step / L : 1.0, trials, now_s() - t0);
         if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
         if (rc) return rc;
         if (rep.kkt <= tol) { status = CR_OK; break; }
@@ -605,11 +770,17 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
                 since_best = 0;
             }
         }
-        const int64_t todo = std::min<int64_t>(opt.check_every, kmax - k);
-        for (int64_t q = 0; q < todo; ++q) {
-            rc = step_once();
+        if (adaptive && primed) {
+            rc = refresh_eta(true);   // exact FP64 eta(lam^k), eta(lam^{k-1}) after the test
             if (rc) return rc;
         }
+        const int64_t todo = std::min<int64_t>(opt.check_every, kmax - k);
+        for (int64_t q = 0; q < todo; ++q) {
+            rc = adaptive ? step_adaptive() : step_once();
+            if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
+            if (rc) return rc;
+        }
+        if (status == CR_ENUMERIC) break;
     }
     if (opt.certificate) {
         int rc = check(&rep, true);
@@ -634,6 +805,7 @@ extern "C" int cr_solver_lipschitz(cr_solver *s, double *L, double *sigma2, int3
 extern "C" int cr_solver_set_L(cr_solver *s, double L) {
     if (!s || !(L > 0.0) || !std::isfinite(L)) return CR_EINVAL;
     s->L = L;
+    s->s_step = L;
     s->sigma2 = 0.0;
     return CR_OK;
 }
@@ -646,7 +818,7 @@ extern "C" int cr_solver_iterate(cr_solver *s, int64_t iters) {
         if (rc) return rc;
     }
     for (int64_t q = 0; q < iters; ++q) {
-        int rc = s->step_once();
+        int rc = s->adaptive ? s->step_adaptive() : s->step_once();
         if (rc) return rc;
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess) return CR_EDEVICE;
@@ -773,7 +945,7 @@ static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, d
     cr_solver *s = nullptr;
     rc = cr_solver_create_impl(N, n, x, ybar, delta, &opt, nullptr, dev, &s);
     if (rc) return rc;
-    if (opt.L > 0.0) s->L = opt.L;
+    if (opt.L > 0.0) { s->L = opt.L; s->s_step = opt.L; }
     cr_report r;
     int status = s->solve(tol, &r);
     if (status != CR_OK && status != CR_ENOCONV && status != CR_ENUMERIC) {

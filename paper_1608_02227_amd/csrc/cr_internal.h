@@ -19,7 +19,10 @@ struct cr_solver {
     bool fp32pass = false;       // current pass arithmetic is FP32
 
     // device buffers (padded as described by Geometry)
-    void *lam[2] = {nullptr, nullptr};   // per iterate: FP64 matrix, or FP32 low part (split)
+    // Multiplier buffers (FP64 matrix, or FP32 low part against lam_hi).  Roles: lam[cur] = lam^k,
+    // lam[prv] = lam^{k-1}; the adaptive step writes its two candidates to lam[fa], lam[fb].
+    void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
+    int prv = 1, fa = 2, fb = 3;
     void *lam_hi = nullptr;              // split: shared high part
     double *ubase = nullptr, *wbase = nullptr;   // split: FP64 C^T H
     double *xhat64 = nullptr, *ybar64 = nullptr;
@@ -29,6 +32,17 @@ struct cr_solver {
     double *yr = nullptr, *xir = nullptr, *dmyr = nullptr;         // scratch primal (repair, prime)
     double *rowred = nullptr;
     void *part_acc = nullptr, *part_col = nullptr;
+    // adaptive step: second set of partials, adjoints of the two candidate differences, and the
+    // FP64 primal points eta(lam^k) (index ecur) and eta(lam^{k-1}) (index 1 - ecur)
+    void *part_acc2 = nullptr, *part_col2 = nullptr;
+    double *uD[2] = {nullptr, nullptr}, *wD[2] = {nullptr, nullptr};
+    double *ye[2] = {nullptr, nullptr}, *xie[2] = {nullptr, nullptr}, *dmye[2] = {nullptr, nullptr};
+    int ecur = 0;
+    bool adaptive = false;
+    double upsilon = 2.0;
+    double s_step = 0.0;         // s_k of the adaptive rule (starts at L)
+    double trials = 0.0;
+    double restarts = 0.0;
     double *part_red = nullptr, *part_min = nullptr;
     int *part_arg = nullptr;
     double *scal = nullptr;
@@ -39,7 +53,7 @@ struct cr_solver {
     double L = 0.0, sigma2 = 0.0, preprocess_s = 0.0;
     int power_iters = 0;
     int64_t k = 0, k_low = 0, checked_k = -1;
-    int cur = 0;                 // buffer holding lam^k; the other holds lam^{k-1}
+    int cur = 0;                 // buffer holding lam^k
     double t = 1.0;              // t_{k+1}
     double beta_last = 0.0;      // beta_k (0 before the first iteration)
     bool primed = false;
@@ -60,6 +74,8 @@ struct cr_solver {
     int rebase();
     int prime();
     int step_once();
+    int step_adaptive();
+    int refresh_eta(bool have_cur_in_yc);
     int lipschitz(double *L, double *s2, int32_t *it);
     int check(cr_report *rep, bool certificate);
     int promote();
@@ -68,11 +84,11 @@ struct cr_solver {
 
 int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
                           const cr_options *opt, const double *lambda0, bool on_device, cr_solver **out);
-size_t cr_state_bytes(int64_t N, int64_t n, int precision);
+size_t cr_state_bytes(int64_t N, int64_t n, int precision, bool adaptive);
 
 namespace cr {
-// y = (1 + b) ya - b yb, xi likewise, dmy = xi^T x - y; float copies when given.
-hipError_t launch_combine(const Geometry &g, const double *ya, const double *xia, const double *yb,
-                          const double *xib, const double *ybar, const double *xhat64, double b, double *y,
-                          double *xi, double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st);
+// y = cya ya + cyb yb, xi = cxa xia + cxb xib, dmy = xi^T x - y (FP64); float copies when given.
+hipError_t launch_lincomb(const Geometry &g, const double *ya, const double *xia, const double *yb,
+                          const double *xib, double cya, double cyb, double cxa, double cxb, const double *xhat64,
+                          double *y, double *xi, double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st);
 }  // namespace cr

@@ -24,8 +24,11 @@ enum PassMode : int {
     PASS_POWER = 3,  // z = C v and C^T z (power iteration), plus ||z||^2
     PASS_REPAIR = 4, // column minima of s and their arg-min rows (max-affine repair)
     PASS_RESID = 5,  // writes s = C eta (FP64, zero diagonal and padding) into lam_b
-    PASS_REBASE = 6  // split forms: H <- round(H + l_k), both low parts re-expressed against the
+    PASS_REBASE = 6, // split forms: H <- round(H + l_k), both low parts re-expressed against the
                      // new H, and the FP64 adjoint of the new H (cached for the next steps)
+    PASS_TRIAL = 7   // adaptive step: two Step-2 candidates lam~ - s / s_a and lam~ - s / s_b from
+                     // one read of the iterates, written to lam_c / lam_d, with the adjoints of
+                     // D = candidate - lam~ (part_acc / part_acc2) and ||D||^2 (part_red slots 0, 1)
 };
 
 // Tiling shared by host and device code.
@@ -89,7 +92,13 @@ struct PassArgs {
     int *part_arg;
     double beta_prev;   // beta_{k-1}: lam~^k = lam^{k-1} + beta_{k-1} (lam^{k-1} - lam^{k-2})
     double beta_next;   // beta_k:     lam~^{k+1} = lam^k + beta_k (lam^k - lam^{k-1})
-    double inv_L;       // 1 / L
+    double inv_L;       // 1 / L (TRIAL: 1 / s_a)
+    // PASS_TRIAL only
+    void *lam_c;        // candidate a (REP_F64: matrix; split: low part against lam_h)
+    void *lam_d;        // candidate b
+    double inv_L2;      // 1 / s_b
+    void *part_acc2;    // adjoint partials of candidate b's difference
+    void *part_col2;
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,

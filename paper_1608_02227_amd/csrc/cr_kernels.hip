@@ -23,6 +23,8 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 namespace cr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -98,6 +100,24 @@ template <> __device__ __forceinline__ void hi_set<REP_SPLIT_BF16>(Raw<REP_SPLIT
 
 template <typename T> __device__ __forceinline__ T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
 
+// Sum over each row of 16 lanes with DPP row shifts (pure VALU, no LDS): after shifts by 1, 2, 4
+// and 8 (lanes shifted in from outside the row read 0), lane 15 of every row holds the row total.
+template <int CTRL> __device__ __forceinline__ float dpp_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_shr(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <typename T> __device__ __forceinline__ T row16_sum(T v) {
+    v += dpp_shr<0x111>(v);   // row_shr:1
+    v += dpp_shr<0x112>(v);   // row_shr:2
+    v += dpp_shr<0x114>(v);   // row_shr:4
+    v += dpp_shr<0x118>(v);   // row_shr:8
+    return v;
+}
+
 // ---- the pair sweep -----------------------------------------------------------------------
 template <typename T, int REP, int MODE, int MB>
 __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry g) {
@@ -112,11 +132,14 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     constexpr int TW = 4 * CPL;                      // tile width (columns)
     constexpr int TPS = kSuper / TW;                 // tiles per super tile
     constexpr bool kSplit = (REP != REP_F64);
-    constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER || MODE == PASS_REBASE);
+    constexpr bool kTrial = (MODE == PASS_TRIAL);
+    constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER || MODE == PASS_REBASE ||
+                               kTrial);
     constexpr bool kResidual = (MODE != PASS_ADJ && MODE != PASS_REBASE);
     constexpr bool kColRed = kAdjoint || MODE == PASS_REPAIR;
-    constexpr bool kReadA = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT || MODE == PASS_REBASE);
-    constexpr bool kReadB = (MODE == PASS_STEP || MODE == PASS_REBASE);
+    constexpr bool kReadA = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT || MODE == PASS_REBASE ||
+                             kTrial);
+    constexpr bool kReadB = (MODE == PASS_STEP || MODE == PASS_REBASE || kTrial);
     constexpr bool kReadH = kSplit && kReadA;
     constexpr bool kLoads = kReadA || kReadB;
     typedef typename Vec4<T>::type V4;
@@ -124,6 +147,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     __shared__ T sX[2 * BUF];
     __shared__ T sY[2 * kSuper];
     __shared__ T sCol[kColRed ? 2 * kWaves * kSuper : 1];
+    __shared__ T sCol2[kTrial ? 2 * kWaves * kSuper : 1];
     __shared__ int sArg[MODE == PASS_REPAIR ? 2 * kWaves * kSuper : 1];
     __shared__ double sRed[kWaves * kRed];
 
@@ -141,7 +165,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     const int cbeg = chunk * g.chunk_cols;
     const int cend = min(g.ld, cbeg + g.chunk_cols);
     const int nsup = (cend - cbeg) / kSuper;
-    const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L;
+    const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L, invL2 = (T)a.inv_L2;
     // Output rows of the 16x16x4 MFMA: lane group g, item v receives row 4 g + v in the FP32 form
     // and row 4 v + g in the FP64 form.  A-row rho is therefore fed the source that lane group
     // g(rho), item v(rho) must see: feature 16 mb + 4 g + v in the adjoint contraction, column
@@ -159,8 +183,11 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     const T dmy_i = kResidual ? dmy[i] : (T)0;
 
     V4 acc[MB];
+    V4 acc2[kTrial ? MB : 1];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[mb] = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int mb = 0; mb < (kTrial ? MB : 1); ++mb) acc2[mb] = V4{0, 0, 0, 0};
     double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
 
     const size_t rowoff = (size_t)i * g.ld;
@@ -170,6 +197,10 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     float *pb32 = static_cast<float *>(a.lam_b);
     float *phf = static_cast<float *>(a.lam_h);
     uint16_t *phb = static_cast<uint16_t *>(a.lam_h);
+    double *pc64 = static_cast<double *>(a.lam_c);
+    double *pd64 = static_cast<double *>(a.lam_d);
+    float *pc32 = static_cast<float *>(a.lam_c);
+    float *pd32 = static_cast<float *>(a.lam_d);
 
     auto load_tile = [&](int j0, Raw<REP> &t) {
         const size_t e = rowoff + j0;
@@ -250,16 +281,25 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             }
 
             T out[CPL];
+            T out2[kTrial ? CPL : 1];
+            T cand_a[kTrial ? CPL : 1], cand_b[kTrial ? CPL : 1];
+            // Pair validity (i != j, both real points) only varies inside tiles that touch the
+            // diagonal or the padding; every other tile takes the unmasked path.  The branch is
+            // uniform over the wave and holds no memory operation.
+            const int i0w = strip * kRows + w * 16;
+            const int jt0 = cst + jl;
+            const bool interior = (i0w + 16 <= g.N) && (jt0 + TW <= g.N) && (i0w + 16 <= jt0 || jt0 + TW <= i0w);
+            auto epilogue = [&](auto masked) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int j = j0 + c;
-                const bool ok = row_ok && (j < g.N) && (j != i);
+                const bool ok = masked ? (row_ok && (j < g.N) && (j != i)) : true;
                 const T s = (sYb[jc + c] + dmy_i) - S[c >> 2][c & 3];
                 if constexpr (MODE == PASS_STEP && REP == REP_F64) {
                     const T P = (T)cur.p[c], Q = (T)cur.q[c];
                     const T lt = P + bp * (P - Q);                       // lam~^k
                     T ln = lt - s * invL;                                // Step 2
-                    ln = ln > (T)0 ? ln : (T)0;
+                    ln = fmax(ln, (T)0);
                     ln = ok ? ln : (T)0;
                     cur.q[c] = (double)ln;                               // lam^k (stored below)
                     const T nx = ln + bn * (ln - P);                     // Step 4
@@ -270,11 +310,42 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
                     const T lt = l1 + bp * (l1 - l2);                    // low part of lam~^k
                     T l0 = lt - s * invL;                                // Step 2 ...
-                    l0 = l0 > -H ? l0 : -H;                              // ... projected: H + l0 >= 0
+                    l0 = fmax(l0, -H);                                   // ... projected: H + l0 >= 0
                     l0 = ok ? l0 : (T)0;
                     cur.b[c >> 2][c & 3] = (float)l0;
                     const T nx = l0 + bn * (l0 - l1);                    // low part of lam~^{k+1}
                     out[c] = ok ? nx : (T)0;
+                } else if constexpr (MODE == PASS_TRIAL && REP == REP_F64) {
+                    const T P = (T)cur.p[c], Q = (T)cur.q[c];
+                    const T lt = P + bp * (P - Q);                       // lam~^k
+                    T ta = fmax(lt - s * invL, (T)0);                    // candidate with 1 / s_a
+                    T tb = fmax(lt - s * invL2, (T)0);                   // candidate with 1 / s_b
+                    ta = ok ? ta : (T)0;
+                    tb = ok ? tb : (T)0;
+                    cand_a[c] = ta;
+                    cand_b[c] = tb;
+                    out[c] = ok ? ta - lt : (T)0;                        // D_a
+                    out2[c] = ok ? tb - lt : (T)0;                       // D_b
+                    red0 += (double)out[c] * (double)out[c];
+                    red1 += (double)out2[c] * (double)out2[c];
+                    red2 += (double)out[c] * (double)(ta - P);           // <D_a, cand_a - lam^k>
+                    red3 += (double)out2[c] * (double)(tb - P);
+                } else if constexpr (MODE == PASS_TRIAL) {
+                    const T H = (T)hi_at<REP>(cur, c);
+                    const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
+                    const T lt = l1 + bp * (l1 - l2);                    // low part of lam~^k
+                    T la = fmax(lt - s * invL, -H);
+                    T lb = fmax(lt - s * invL2, -H);
+                    la = ok ? la : (T)0;
+                    lb = ok ? lb : (T)0;
+                    cand_a[c] = la;
+                    cand_b[c] = lb;
+                    out[c] = ok ? la - lt : (T)0;
+                    out2[c] = ok ? lb - lt : (T)0;
+                    red0 += (double)out[c] * (double)out[c];
+                    red1 += (double)out2[c] * (double)out2[c];
+                    red2 += (double)out[c] * (double)(la - l1);          // <D_a, cand_a - lam^k>
+                    red3 += (double)out2[c] * (double)(lb - l1);
                 } else if constexpr (MODE == PASS_ADJ) {
                     T v;
                     if constexpr (REP == REP_F64) v = (T)cur.p[c];
@@ -316,9 +387,24 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     out[c] = (T)0;
                 }
             }
+            };
+            if (interior) epilogue(std::false_type{});
+            else epilogue(std::true_type{});
             {
                 const size_t e = rowoff + j0;
-                if constexpr (REP == REP_F64) {
+                if constexpr (kTrial) {
+                    if constexpr (REP == REP_F64) {
+                        *reinterpret_cast<d4 *>(pc64 + e) = d4{(double)cand_a[0], (double)cand_a[1],
+                                                               (double)cand_a[2], (double)cand_a[3]};
+                        *reinterpret_cast<d4 *>(pd64 + e) = d4{(double)cand_b[0], (double)cand_b[1],
+                                                               (double)cand_b[2], (double)cand_b[3]};
+                    } else {
+                        *reinterpret_cast<f4 *>(pc32 + e) = f4{(float)cand_a[0], (float)cand_a[1], (float)cand_a[2], (float)cand_a[3]};
+                        *reinterpret_cast<f4 *>(pc32 + e + 4) = f4{(float)cand_a[4], (float)cand_a[5], (float)cand_a[6], (float)cand_a[7]};
+                        *reinterpret_cast<f4 *>(pd32 + e) = f4{(float)cand_b[0], (float)cand_b[1], (float)cand_b[2], (float)cand_b[3]};
+                        *reinterpret_cast<f4 *>(pd32 + e + 4) = f4{(float)cand_b[4], (float)cand_b[5], (float)cand_b[6], (float)cand_b[7]};
+                    }
+                } else if constexpr (REP == REP_F64) {
                     if (MODE == PASS_STEP || MODE == PASS_RESID) *reinterpret_cast<d4 *>(pb64 + e) = cur.q;
                 } else {
                     if (MODE == PASS_STEP || MODE == PASS_REBASE) {
@@ -346,14 +432,23 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                         acc[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out[c], acc[mb]);
                 T cs[CPL];
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) cs[c] = out[c];
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1)
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) cs[c] += shfl_xor(cs[c], m);
-                if (lr == 0) {
+                for (int c = 0; c < CPL; ++c) cs[c] = row16_sum(out[c]);
+                if (lr == 15) {
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) sCol[(b * kWaves + w) * kSuper + jc + c] = cs[c];
+                }
+                if constexpr (kTrial) {
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            acc2[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out2[c], acc2[mb]);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) cs[c] = row16_sum(out2[c]);
+                    if (lr == 15) {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) sCol2[(b * kWaves + w) * kSuper + jc + c] = cs[c];
+                    }
                 }
             } else if (MODE == PASS_REPAIR) {
                 // column minimum over the 16 rows of this wave, lowest row on ties
@@ -408,13 +503,19 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 T v = sCol[base + tid];
                 for (int ww = 1; ww < kWaves; ++ww) v += sCol[base + ww * kSuper + tid];
                 static_cast<T *>(a.part_col)[(size_t)strip * g.ld + j] = v;
+                if constexpr (kTrial) {
+                    T v2 = sCol2[base + tid];
+                    for (int ww = 1; ww < kWaves; ++ww) v2 += sCol2[base + ww * kSuper + tid];
+                    static_cast<T *>(a.part_col2)[(size_t)strip * g.ld + j] = v2;
+                }
             }
         }
     }
 
     if (kAdjoint) {
-        // D layout: lane (lr, lq) holds rows m = 16 mb + 4 lq + v of (Lam Xhat)^T for row i.
+        // D layout: lane (lr, lq) holds rows m = 16 mb + 4 lq + r of (Lam Xhat)^T for row i.
         T *pacc = static_cast<T *>(a.part_acc) + ((size_t)chunk * g.Nr + i) * NP;
+        T *pacc2 = kTrial ? static_cast<T *>(a.part_acc2) + ((size_t)chunk * g.Nr + i) * NP : nullptr;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             if (sizeof(T) == 8) {
@@ -424,13 +525,22 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 *reinterpret_cast<f4 *>(reinterpret_cast<float *>(pacc) + 16 * mb + 4 * lq) =
                     f4{(float)acc[mb][0], (float)acc[mb][1], (float)acc[mb][2], (float)acc[mb][3]};
             }
+            if constexpr (kTrial) {
+                if (sizeof(T) == 8) {
+                    *reinterpret_cast<d4 *>(reinterpret_cast<double *>(pacc2) + 16 * mb + 4 * lq) =
+                        d4{(double)acc2[mb][0], (double)acc2[mb][1], (double)acc2[mb][2], (double)acc2[mb][3]};
+                } else {
+                    *reinterpret_cast<f4 *>(reinterpret_cast<float *>(pacc2) + 16 * mb + 4 * lq) =
+                        f4{(float)acc2[mb][0], (float)acc2[mb][1], (float)acc2[mb][2], (float)acc2[mb][3]};
+                }
+            }
         }
     }
 
-    if (MODE == PASS_KKT || MODE == PASS_POWER) {
+    if (MODE == PASS_KKT || MODE == PASS_POWER || kTrial) {
         for (int m = 32; m >= 1; m >>= 1) {
             red0 = (MODE == PASS_KKT) ? fmax(red0, __shfl_xor(red0, m, 64)) : red0 + __shfl_xor(red0, m, 64);
-            red1 = fmax(red1, __shfl_xor(red1, m, 64));
+            red1 = kTrial ? red1 + __shfl_xor(red1, m, 64) : fmax(red1, __shfl_xor(red1, m, 64));
             red2 += __shfl_xor(red2, m, 64);
             red3 += __shfl_xor(red3, m, 64);
         }
@@ -446,6 +556,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             for (int ww = 1; ww < kWaves; ++ww) {
                 const double o = sRed[ww * kRed + tid];
                 if (MODE == PASS_KKT && tid < 2) v = fmax(v, o);
+                else if (MODE == PASS_POWER && tid == 1) v = fmax(v, o);
                 else v += o;
             }
             a.part_red[(size_t)blockIdx.x * kRed + tid] = v;
@@ -538,6 +649,11 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, 
     case PASS_RESID:
         if (fp32 || rep != REP_F64) return hipErrorInvalidValue;
         return launch_mb<double, REP_F64, PASS_RESID>(g, a, st);
+    case PASS_TRIAL:
+        if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_TRIAL>(g, a, st);
+        if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_TRIAL>(g, a, st);
+        if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_TRIAL>(g, a, st);
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
@@ -894,32 +1010,31 @@ hipError_t launch_unpad_primal(const Geometry &g, const double *y, const double 
     return hipGetLastError();
 }
 
-__global__ void combine_kernel(const double *ya, const double *xia, const double *yb, const double *xib,
-                               const double *xhat64, double b, double *y, double *xi, double *dmy, float *y32,
-                               float *xi32, float *dmy32, int N, int n, int Nr, int NP) {
+__global__ void lincomb_kernel(const double *ya, const double *xia, const double *yb, const double *xib, double cya,
+                               double cyb, double cxa, double cxb, const double *xhat64, double *y, double *xi,
+                               double *dmy, float *y32, float *xi32, float *dmy32, int N, int n, int Nr, int NP) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nr) return;
     double d = 0.0;
     for (int m = 0; m < NP; ++m) {
         const size_t e = (size_t)i * NP + m;
-        const double v = (1.0 + b) * xia[e] - b * xib[e];
+        const double v = cxa * xia[e] + cxb * xib[e];
         xi[e] = v;
         if (xi32) xi32[e] = (float)v;
         if (m < n) d += v * xhat64[e];
     }
-    const double yy = (1.0 + b) * ya[i] - b * yb[i];
+    const double yy = cya * ya[i] + cyb * yb[i];
     y[i] = yy;
     dmy[i] = i < N ? d - yy : 0.0;
     if (y32) y32[i] = (float)yy;
     if (dmy32) dmy32[i] = i < N ? (float)(d - yy) : 0.f;
 }
 
-hipError_t launch_combine(const Geometry &g, const double *ya, const double *xia, const double *yb,
-                          const double *xib, const double *ybar, const double *xhat64, double b, double *y,
-                          double *xi, double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st) {
-    (void)ybar;
-    hipLaunchKernelGGL(combine_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, ya, xia, yb, xib, xhat64, b, y,
-                       xi, dmy, y32, xi32, dmy32, g.N, g.n, g.Nr, g.NP);
+hipError_t launch_lincomb(const Geometry &g, const double *ya, const double *xia, const double *yb,
+                          const double *xib, double cya, double cyb, double cxa, double cxb, const double *xhat64,
+                          double *y, double *xi, double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st) {
+    hipLaunchKernelGGL(lincomb_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, ya, xia, yb, xib, cya, cyb, cxa,
+                       cxb, xhat64, y, xi, dmy, y32, xi32, dmy32, g.N, g.n, g.Nr, g.NP);
     return hipGetLastError();
 }
 

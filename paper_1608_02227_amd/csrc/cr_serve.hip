@@ -113,8 +113,9 @@ struct cr_ctx {
 
 extern "C" size_t cr_fit_state_bytes(int64_t N, int64_t n, int32_t precision) {
     if (N < 1 || n < 1 || n + 1 > 16 * cr::kMaxMB || precision < CR_FP64 || precision > CR_MIXED_BF16) return 0;
-    size_t b = cr_state_bytes(N, n, precision);
-    if (precision != CR_FP64) b += cr_state_bytes(N, n, CR_FP64);   // promotion peak
+    // the default (adaptive) step rule; it needs more than the constant step
+    size_t b = cr_state_bytes(N, n, precision, true);
+    if (precision != CR_FP64) b += cr_state_bytes(N, n, CR_FP64, true);   // promotion peak
     return b;
 }
 
@@ -173,7 +174,10 @@ extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const
     r->delta = delta;
     r->tol = tol;
     if (opt) r->opt = *opt; else cr_default_options(&r->opt);
-    r->bytes = cr_fit_state_bytes(N, n, r->opt.precision);
+    if (r->opt.precision < CR_FP64 || r->opt.precision > CR_MIXED_BF16) return CR_EINVAL;
+    const bool adaptive = r->opt.step_rule != 0;
+    r->bytes = cr_state_bytes(N, n, r->opt.precision, adaptive);
+    if (r->opt.precision != CR_FP64) r->bytes += cr_state_bytes(N, n, CR_FP64, adaptive);   // promotion peak
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(c->mu);
     if (r->bytes > c->budget) return CR_ENOMEM;

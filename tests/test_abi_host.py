@@ -36,6 +36,7 @@ def test_strerror_and_defaults(cr):
     o = cr.CROptions()
     cr.load().cr_default_options(C.byref(o))
     assert o.check_every == 50 and o.momentum == 1 and o.precision == 0 and o.power_max_iters == 300
+    assert o.step_rule == 1 and o.upsilon == 2.0 and o.restart == 1
 
 
 @pytest.mark.parametrize("N,n,delta,tol", [(0, 2, 1e-3, 1e-4), (10, 0, 1e-3, 1e-4), (10, 2, 0.0, 1e-4),
@@ -58,7 +59,8 @@ def test_fit_rejects_bad_options_on_host(cr):
     yb = np.zeros(4)
     y = np.zeros(4)
     xi = np.zeros((4, 2))
-    for field, value in [("check_every", 0), ("precision", 7), ("L", -1.0), ("power_max_iters", 0)]:
+    for field, value in [("check_every", 0), ("precision", 7), ("L", -1.0), ("power_max_iters", 0),
+                         ("step_rule", 2), ("upsilon", 1.0), ("upsilon", float("inf")), ("restart", 2)]:
         opt = cr.Options().to_c()
         setattr(opt, field, value)
         rc = lib.cr_fit(4, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)

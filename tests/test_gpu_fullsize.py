@@ -60,7 +60,7 @@ def test_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
     x, ybar = quad8000
     delta = 1e-3
     rows = np.random.default_rng(0).choice(8000, 48, replace=False)
-    with cr.Solver(x, ybar, delta, cr.Options(precision=precision)) as s:
+    with cr.Solver(x, ybar, delta, cr.Options(precision=precision, step_rule="constant")) as s:
         L, s2, _ = s.lipschitz()
         a2 = _a2_norm2(x)
         assert a2 * (1 - 1e-6) <= s2 <= 2 * 8000 + a2          # Lemma lem:O1-constant
@@ -74,6 +74,47 @@ def test_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
     scale = np.abs(ref).max()
     assert scale > 0
     assert np.max(np.abs(got - ref)) <= rtol * scale
+    assert np.all(got >= 0.0)
+
+
+def _oracle_adaptive_step(x, ybar, delta, s_prev, lam_km1, lam_km2, k, upsilon=2.0):
+    """One adaptive-step P-APG iteration (Section 2.4): returns (s_k, lam^k)."""
+    _, beta = oracle.fista_schedule(k)
+    b = beta[k - 1] if k >= 2 else 0.0
+    lt = lam_km1 + b * (lam_km1 - lam_km2)
+    y, xi = oracle.primal_from_dual(x, ybar, delta, lt)
+    s = oracle.pair_residual(x, y, xi)
+    ell = 0
+    while True:
+        s_try = s_prev * upsilon ** (ell - 1)
+        lam = np.maximum(0.0, lt - s / s_try)
+        np.fill_diagonal(lam, 0.0)
+        D = lam - lt
+        du, dw = oracle.pair_adjoint(x, D)
+        if float(du @ du) + float(np.sum(dw * dw)) / delta <= s_try * float(np.sum(D * D)) * (1.0 + 1e-12):
+            return s_try, lam
+        ell += 1
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed_fp32", 1e-5)])
+def test_adaptive_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
+    x, ybar = quad8000
+    delta = 1e-3
+    rows = np.random.default_rng(2).choice(8000, 48, replace=False)
+    with cr.Solver(x, ybar, delta, cr.Options(precision=precision, restart=False)) as s:
+        s.lipschitz()
+        s.iterate(4)
+        lam4 = s.lam()
+        s.iterate(1)
+        lam5 = s.lam()
+        s5 = s.report()["step_final"]
+        s.iterate(1)
+        s6 = s.report()["step_final"]
+        got = np.vstack([s.lam_rows(int(r), 1) for r in rows])
+    s6_ref, lam6 = _oracle_adaptive_step(x, ybar, delta, s5, lam5, lam4, 6)
+    assert s6 == s6_ref
+    ref = lam6[rows]
+    assert np.max(np.abs(got - ref)) <= rtol * np.abs(ref).max()
     assert np.all(got >= 0.0)
 
 
@@ -100,7 +141,7 @@ def test_large_fit_N40000(cr, torch_dev):
     N = x.shape[0]
     delta = 1e-3
     rows = np.random.default_rng(1).choice(N, 16, replace=False)
-    with cr.Solver(x, ybar, delta, cr.Options(precision="mixed_fp32")) as s:
+    with cr.Solver(x, ybar, delta, cr.Options(precision="mixed_fp32", step_rule="constant")) as s:
         L, s2, _ = s.lipschitz()
         assert 0.0 < s2 <= 2 * N + _a2_norm2(x)
         s.iterate(1)

@@ -441,3 +441,44 @@ def test_adaptive_accepted_steps_satisfy_the_check_and_beat_constant_steps():
     c = oracle.papg(x, ybar, gamma, 0.0, L=L, max_iters=150, check_every=150)
     assert a["report"]["dual_obj"] >= c["report"]["dual_obj"]
     assert min(steps) < L
+
+
+# --- momentum restart (an option beyond the paper, on top of the adaptive step) ---------------
+
+@pytest.mark.parametrize("N,n,seed,gamma", [(12, 1, 0, 1e-1), (15, 2, 1, 1e-2), (10, 2, 3, 1e-3)])
+def test_adaptive_restart_matches_exact_nnls(N, n, seed, gamma):
+    x, ybar = _rand_problem(N, n, seed)
+    ex = exact_solve(x, ybar, gamma)
+    r = oracle.papg(x, ybar, gamma, 1e-11, max_iters=400000, check_every=50, adaptive=True, restart=True)
+    assert r["status"] == "converged"
+    scale = max(1.0, np.abs(ex["y"]).max())
+    np.testing.assert_allclose(r["y"], ex["y"], rtol=0, atol=1e-8 * scale)
+
+
+def test_restart_resets_the_momentum_where_the_step_opposes_the_movement():
+    # Re-derive every iterate of the restarted run from its accepted steps with an independent
+    # restart rule: after an iteration with <lam^k - lam~^k, lam^k - lam^{k-1}> < 0 the FISTA
+    # sequence starts again at t = 1, so the next extrapolation weight is zero.
+    x, ybar = W.sq_norm(40, 2, 0.1, 6)
+    gamma = 1e-3
+    L, _, _ = oracle.lipschitz(x, gamma)
+    its, steps = [], []
+    oracle.papg(x, ybar, gamma, 0.0, L=L, max_iters=300, check_every=10 ** 9, adaptive=True, restart=True,
+                iterates=its, steps=steps)
+    prev = np.zeros((40, 40))
+    prev2 = np.zeros((40, 40))
+    t, b, restarts = 1.0, 0.0, 0
+    for (k, lam), s in zip(its, steps):
+        lt = prev + b * (prev - prev2)
+        y, xi = oracle.primal_from_dual(x, ybar, gamma, lt)
+        ref = np.maximum(0.0, lt - oracle.pair_residual(x, y, xi) / s)
+        np.fill_diagonal(ref, 0.0)
+        np.testing.assert_allclose(lam, ref, rtol=0, atol=1e-15)
+        if np.sum((lam - lt) * (lam - prev)) < 0.0:
+            t = 1.0
+            restarts += 1
+        t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        b = (t - 1.0) / t_next
+        t = t_next
+        prev2, prev = prev, lam
+    assert restarts > 0
