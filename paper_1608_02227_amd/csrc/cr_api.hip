@@ -59,7 +59,7 @@ extern "C" void cr_default_options(cr_options *opt) {
     opt->time_budget_s = 0.0;
     opt->L = 0.0;
     opt->power_max_iters = 300;
-    opt->power_rtol = 1e-8;
+    opt->power_rtol = 0.0;   // automatic: 1e-8 for the constant step, 1e-4 for the adaptive one
     opt->momentum = 1;
     opt->certificate = 1;
     opt->device = 0;
@@ -145,6 +145,7 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->precision < CR_FP64 || opt->precision > CR_MIXED_BF16) return CR_EINVAL;
         if (opt->check_every < 1 || opt->max_iters < 0 || opt->power_max_iters < 1) return CR_EINVAL;
         if (opt->L < 0.0 || !std::isfinite(opt->L) || opt->time_budget_s < 0.0) return CR_EINVAL;
+        if (!(opt->power_rtol >= 0.0) || !std::isfinite(opt->power_rtol)) return CR_EINVAL;
         if (opt->step_rule < 0 || opt->step_rule > 1) return CR_EINVAL;
         if (opt->step_rule == 1 && !(opt->upsilon > 1.0 && std::isfinite(opt->upsilon))) return CR_EINVAL;
         if (opt->restart < 0 || opt->restart > 1) return CR_EINVAL;
@@ -245,6 +246,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     if (s->adaptive) {
         CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
         CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
+        CR_ALLOC(s->block_part, (size_t)(g.Nr / 16) * 4 * 8);
         for (int q = 0; q < 2; ++q) {
             CR_ALLOC(s->uD[q], nr * 8);
             CR_ALLOC(s->wD[q], rows_np * 8);
@@ -476,20 +478,17 @@ int cr_solver::step_adaptive() {
             ev_pending = true;
             ev_pending_low = fp32pass;
         }
-        for (int q = 0; q < 2; ++q) {
-            FinalizeArgs f{};
-            f.part_acc = q ? part_acc2 : part_acc;
-            f.part_col = q ? part_col2 : part_col;
-            f.xf = xhat64;
-            f.ybar = ybar64;
-            f.y = uD[q]; f.xi = wD[q]; f.dmy = dmyr;
-            f.rowred = rowred;
-            f.inv_delta = 1.0;
-            f.power = 1;
-            CR_HIP(launch_finalize(g, fp32pass, f, stream));
-            CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 2 * q, stream));
-        }
-        CR_HIP(launch_reduce(part_red, g.grid(), kRed, 0, 4, scal + 4, stream));
+        TrialFinalizeArgs f{};
+        f.part_acc[0] = part_acc; f.part_acc[1] = part_acc2;
+        f.part_col[0] = part_col; f.part_col[1] = part_col2;
+        f.xf = xhat64;
+        f.uD[0] = uD[0]; f.uD[1] = uD[1];
+        f.wD[0] = wD[0]; f.wD[1] = wD[1];
+        f.block_part = block_part;
+        CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
+        // scal: ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b, ||D_a||^2, ||D_b||^2,
+        //       <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>
+        CR_HIP(launch_reduce2(block_part, g.Nr / 16, 4, 4, part_red, g.grid(), kRed, 4, scal, stream));
         CR_HIP(hipMemcpyAsync(h_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
         CR_HIP(hipStreamSynchronize(stream));
         collect_timing();
@@ -503,11 +502,6 @@ int cr_solver::step_adaptive() {
         sb = sa * upsilon;
     }
     if (accepted < 0) return CR_ENUMERIC;   // no admissible step after 2^128-fold growth
-    // eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta), into the slot of eta(lam^{k-1})
-    const int en = 1 - ecur;
-    CR_HIP(launch_lincomb(g, y64, xi64, uD[accepted], wD[accepted], 1.0, 1.0, 1.0, 1.0 / delta, xhat64, ye[en],
-                          xie[en], dmye[en], nullptr, nullptr, nullptr, stream));
-    ecur = en;
     const int c = cur, p = prv, A = fa, B = fb;
     if (accepted == 0) { cur = A; prv = c; fa = p; fb = B; }
     else { cur = B; prv = c; fa = A; fb = p; }
@@ -518,9 +512,13 @@ int cr_solver::step_adaptive() {
     }
     const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
     const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
-    CR_HIP(launch_lincomb(g, ye[ecur], xie[ecur], ye[1 - ecur], xie[1 - ecur], 1.0 + beta_k, -beta_k, 1.0 + beta_k,
-                          -beta_k, xhat64, y64, xi64, dmy64, fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr,
-                          fp32pass ? dmy32 : nullptr, stream));
+    // eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta) into the slot of eta(lam^{k-1}),
+    // and the pass arrays (1 + beta_k) eta(lam^{k+1}) - beta_k eta(lam^k) for the next iteration
+    const int en = 1 - ecur;
+    CR_HIP(launch_accept(g, y64, xi64, dmy64, uD[accepted], wD[accepted], ye[ecur], xie[ecur], ye[en], xie[en],
+                         dmye[en], fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr, fp32pass ? dmy32 : nullptr,
+                         xhat64, 1.0 / delta, beta_k, stream));
+    ecur = en;
     t = t_next;
     beta_last = beta_k;
     s_step = s_new;
@@ -595,6 +593,9 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
     const double t0 = now_s();
     CR_HIP(hipSetDevice(device));
     CR_HIP(launch_power_init(g, xhat64, y64, xi64, dmy64, stream));
+    // The constant step 1/L needs L itself; the adaptive rule only starts from s_0 = L and checks
+    // every step, so a coarser estimate serves it.
+    const double rtol = opt.power_rtol > 0.0 ? opt.power_rtol : (adaptive ? 1e-4 : 1e-8);
     double est = 0.0;
     int it = 0;
     for (it = 1; it <= opt.power_max_iters; ++it) {
@@ -614,7 +615,7 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
         const double nw = h_scal[0];
         if (!std::isfinite(nw)) return CR_ENUMERIC;
         if (h_scal[1] + h_scal[2] == 0.0) { est = nw; break; }
-        const bool done = std::fabs(nw - est) <= opt.power_rtol * nw;
+        const bool done = std::fabs(nw - est) <= rtol * nw;
         est = nw;
         if (done) break;
     }

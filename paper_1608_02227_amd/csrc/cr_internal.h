@@ -35,6 +35,7 @@ struct cr_solver {
     // adaptive step: second set of partials, adjoints of the two candidate differences, and the
     // FP64 primal points eta(lam^k) (index ecur) and eta(lam^{k-1}) (index 1 - ecur)
     void *part_acc2 = nullptr, *part_col2 = nullptr;
+    double *block_part = nullptr;   // per-block sums of the trial finalize
     double *uD[2] = {nullptr, nullptr}, *wD[2] = {nullptr, nullptr};
     double *ye[2] = {nullptr, nullptr}, *xie[2] = {nullptr, nullptr}, *dmye[2] = {nullptr, nullptr};
     int ecur = 0;

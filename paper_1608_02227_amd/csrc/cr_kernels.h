@@ -127,6 +127,29 @@ struct FinalizeArgs {
 };
 hipError_t launch_finalize(const Geometry &g, bool fp32, const FinalizeArgs &a, hipStream_t st);
 
+// Adjoints of both candidate differences of a trial pass (power-mode finalize, no ybar) and
+// per-block partial sums (||A1^T D_0||^2, ||A2^T D_0||^2, ||A1^T D_1||^2, ||A2^T D_1||^2).
+struct TrialFinalizeArgs {
+    const void *part_acc[2];
+    const void *part_col[2];
+    const double *xf;       // Xhat, FP64, Nr x NP
+    double *uD[2];          // Nr
+    double *wD[2];          // Nr x NP
+    double *block_part;     // (Nr / 16) x 4
+};
+hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st);
+
+// Column sums of two partial arrays in one launch (na + nb <= 8 outputs).
+hipError_t launch_reduce2(const double *pa, int ba, int sa, int na, const double *pb, int bb, int sb, int nb,
+                          double *out, hipStream_t st);
+
+// Accepted adaptive step: eta(lam^{k+1}) from eta(lam~^{k+1}) (in y, xi) and the adjoint of D,
+// then the next pass arrays (1 + beta) eta(lam^{k+1}) - beta eta(lam^k).
+hipError_t launch_accept(const Geometry &g, double *y, double *xi, double *dmy, const double *uD, const double *wD,
+                         const double *yk, const double *xik, double *ye, double *xie, double *dmye, float *y32,
+                         float *xi32, float *dmy32, const double *xhat64, double inv_delta, double beta,
+                         hipStream_t st);
+
 // Sums / maxima of per-block partials: out[q] = op_q over blocks of part[b * stride + q],
 // with op = max for q < nmax and sum otherwise.  Single workgroup, deterministic order.
 hipError_t launch_reduce(const double *part, int blocks, int stride, int nmax, int nout,

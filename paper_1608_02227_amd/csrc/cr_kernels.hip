@@ -1010,31 +1010,188 @@ hipError_t launch_unpad_primal(const Geometry &g, const double *y, const double 
     return hipGetLastError();
 }
 
-__global__ void lincomb_kernel(const double *ya, const double *xia, const double *yb, const double *xib, double cya,
-                               double cyb, double cxa, double cxb, const double *xhat64, double *y, double *xi,
-                               double *dmy, float *y32, float *xi32, float *dmy32, int N, int n, int Nr, int NP) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Nr) return;
+// 16 threads per row (features m = t, t + 16, ...), 16 rows per 256-thread block: row segments
+// are read and written as whole 128-byte lines.
+__global__ __launch_bounds__(256) void lincomb_kernel(const double *ya, const double *xia, const double *yb,
+                                                     const double *xib, double cya, double cyb, double cxa,
+                                                     double cxb, const double *xhat64, double *y, double *xi,
+                                                     double *dmy, float *y32, float *xi32, float *dmy32, int N, int n,
+                                                     int Nr, int NP) {
+    const int t = threadIdx.x & 15;
+    const int i = blockIdx.x * 16 + (threadIdx.x >> 4);   // grid covers Nr exactly
     double d = 0.0;
-    for (int m = 0; m < NP; ++m) {
+    for (int m = t; m < NP; m += 16) {
         const size_t e = (size_t)i * NP + m;
         const double v = cxa * xia[e] + cxb * xib[e];
         xi[e] = v;
         if (xi32) xi32[e] = (float)v;
         if (m < n) d += v * xhat64[e];
     }
-    const double yy = cya * ya[i] + cyb * yb[i];
-    y[i] = yy;
-    dmy[i] = i < N ? d - yy : 0.0;
-    if (y32) y32[i] = (float)yy;
-    if (dmy32) dmy32[i] = i < N ? (float)(d - yy) : 0.f;
+    for (int s = 1; s < 16; s <<= 1) d += __shfl_xor(d, s, 16);
+    if (t == 0) {
+        const double yy = cya * ya[i] + cyb * yb[i];
+        y[i] = yy;
+        dmy[i] = i < N ? d - yy : 0.0;
+        if (y32) y32[i] = (float)yy;
+        if (dmy32) dmy32[i] = i < N ? (float)(d - yy) : 0.f;
+    }
 }
 
 hipError_t launch_lincomb(const Geometry &g, const double *ya, const double *xia, const double *yb,
                           const double *xib, double cya, double cyb, double cxa, double cxb, const double *xhat64,
                           double *y, double *xi, double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st) {
-    hipLaunchKernelGGL(lincomb_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, ya, xia, yb, xib, cya, cyb, cxa,
-                       cxb, xhat64, y, xi, dmy, y32, xi32, dmy32, g.N, g.n, g.Nr, g.NP);
+    hipLaunchKernelGGL(lincomb_kernel, dim3(g.Nr / 16), dim3(256), 0, st, ya, xia, yb, xib, cya, cyb, cxa, cxb, xhat64,
+                       y, xi, dmy, y32, xi32, dmy32, g.N, g.n, g.Nr, g.NP);
+    return hipGetLastError();
+}
+
+// Accepted adaptive step: eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta) into
+// (ye, xie, dmye), then the next extrapolated point (1 + beta) eta(lam^{k+1}) - beta eta(lam^k) into
+// the pass arrays (y, xi, dmy and their FP32 copies).  (y, xi) hold eta(lam~^{k+1}) on entry.
+__global__ __launch_bounds__(256) void accept_kernel(double *y, double *xi, double *dmy, const double *uD,
+                                                    const double *wD, const double *yk, const double *xik,
+                                                    double *ye, double *xie, double *dmye, float *y32, float *xi32,
+                                                    float *dmy32, const double *xhat64, double inv_delta, double beta,
+                                                    int N, int n, int NP) {
+    const int t = threadIdx.x & 15;
+    const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
+    double dn = 0.0, dp = 0.0;
+    for (int m = t; m < NP; m += 16) {
+        const size_t e = (size_t)i * NP + m;
+        const double xn = xi[e] + wD[e] * inv_delta;
+        const double xp = (1.0 + beta) * xn - beta * xik[e];
+        xie[e] = xn;
+        xi[e] = xp;
+        if (xi32) xi32[e] = (float)xp;
+        if (m < n) {
+            dn += xn * xhat64[e];
+            dp += xp * xhat64[e];
+        }
+    }
+    for (int s = 1; s < 16; s <<= 1) {
+        dn += __shfl_xor(dn, s, 16);
+        dp += __shfl_xor(dp, s, 16);
+    }
+    if (t == 0) {
+        const bool valid = i < N;
+        const double yn = y[i] + uD[i];
+        const double yp = (1.0 + beta) * yn - beta * yk[i];
+        ye[i] = yn;
+        dmye[i] = valid ? dn - yn : 0.0;
+        y[i] = yp;
+        dmy[i] = valid ? dp - yp : 0.0;
+        if (y32) y32[i] = (float)yp;
+        if (dmy32) dmy32[i] = valid ? (float)(dp - yp) : 0.f;
+    }
+}
+
+hipError_t launch_accept(const Geometry &g, double *y, double *xi, double *dmy, const double *uD, const double *wD,
+                         const double *yk, const double *xik, double *ye, double *xie, double *dmye, float *y32,
+                         float *xi32, float *dmy32, const double *xhat64, double inv_delta, double beta,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, y, xi, dmy, uD, wD, yk, xik, ye, xie, dmye,
+                       y32, xi32, dmy32, xhat64, inv_delta, beta, g.N, g.n, g.NP);
+    return hipGetLastError();
+}
+
+// Both candidates of a trial pass: adjoints (A1^T D_q, A2^T D_q) from the pass partials, like the
+// power-mode finalize, plus per-block sums of ||A1^T D_q||^2 and ||A2^T D_q||^2 (4 per block).
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void trial_finalize_kernel(TrialFinalizeArgs a, Geometry g) {
+    constexpr int NP = 16 * MB;
+    const int t = threadIdx.x & 15;
+    const int r = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + r;
+    const bool valid = i < g.N;
+    __shared__ double sh[16][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const T *pacc = static_cast<const T *>(a.part_acc[q]);
+        const T *pcol = static_cast<const T *>(a.part_col[q]);
+        double lx[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            double s = 0.0;
+            for (int c = 0; c < g.chunks; ++c) s += (double)pacc[((size_t)c * g.Nr + i) * NP + 16 * mb + t];
+            lx[mb] = s;
+        }
+        double mine = 0.0;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+            if (16 * mb + t == g.n) mine = lx[mb];
+        double rsum = mine;
+        for (int m = 1; m < 16; m <<= 1) rsum += __shfl_xor(rsum, m, 16);
+        double csum = 0.0;
+        for (int s = t; s < g.strips; s += 16) csum += (double)pcol[(size_t)s * g.ld + i];
+        for (int m = 1; m < 16; m <<= 1) csum += __shfl_xor(csum, m, 16);
+        const double u = valid ? csum - rsum : 0.0;
+        double wsq = 0.0;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int m = 16 * mb + t;
+            double v = 0.0;
+            if (valid && m < g.n) v = rsum * a.xf[(size_t)i * NP + m] - lx[mb];
+            a.wD[q][(size_t)i * NP + m] = v;
+            wsq += v * v;
+        }
+        for (int m = 1; m < 16; m <<= 1) wsq += __shfl_xor(wsq, m, 16);
+        if (t == 0) {
+            a.uD[q][i] = u;
+            sh[r][2 * q] = u * u;
+            sh[r][2 * q + 1] = wsq;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int rr = 0; rr < 16; ++rr) s += sh[rr][threadIdx.x];
+        a.block_part[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
+    }
+}
+
+hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st) {
+    dim3 grid(g.Nr / 16), block(256);
+#define CR_TFIN(T, MBV) hipLaunchKernelGGL((trial_finalize_kernel<T, MBV>), grid, block, 0, st, a, g)
+    if (fp32) {
+        switch (g.MB) { case 1: CR_TFIN(float, 1); break; case 2: CR_TFIN(float, 2); break;
+                        case 3: CR_TFIN(float, 3); break; case 4: CR_TFIN(float, 4); break;
+                        default: return hipErrorInvalidValue; }
+    } else {
+        switch (g.MB) { case 1: CR_TFIN(double, 1); break; case 2: CR_TFIN(double, 2); break;
+                        case 3: CR_TFIN(double, 3); break; case 4: CR_TFIN(double, 4); break;
+                        default: return hipErrorInvalidValue; }
+    }
+#undef CR_TFIN
+    return hipGetLastError();
+}
+
+// Two independent sets of column sums in one single-workgroup launch, fixed order:
+// out[q] = sum_b a[b * sa + q] for q < na, then out[na + q] = sum_b b[b * sb + q] for q < nb.
+__global__ __launch_bounds__(256) void reduce2_kernel(const double *pa, int ba, int sa, int na, const double *pb,
+                                                     int bb, int sb, int nb, double *out) {
+    __shared__ double sh[8][256];
+    const int nt = na + nb;
+    for (int q = 0; q < nt; ++q) {
+        const bool first = q < na;
+        const double *p = first ? pa : pb;
+        const int blocks = first ? ba : bb, stride = first ? sa : sb, col = first ? q : q - na;
+        double v = 0.0;
+        for (int b = threadIdx.x; b < blocks; b += 256) v += p[(size_t)b * stride + col];
+        sh[q][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < nt; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < nt) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_reduce2(const double *pa, int ba, int sa, int na, const double *pb, int bb, int sb, int nb,
+                          double *out, hipStream_t st) {
+    if (na + nb > 8 || na < 0 || nb < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(256), 0, st, pa, ba, sa, na, pb, bb, sb, nb, out);
     return hipGetLastError();
 }
 

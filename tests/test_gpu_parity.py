@@ -70,7 +70,7 @@ def test_lipschitz_matches_oracle(cr, torch_dev, wl, N, seed):
     x, ybar = W.make(wl, seed=seed, N=N)
     delta = W.WORKLOADS[wl].delta
     L0, s20, it0 = oracle.lipschitz(x, delta)
-    with cr.Solver(x, ybar, delta) as s:
+    with cr.Solver(x, ybar, delta, cr.Options(power_rtol=1e-8)) as s:
         L, s2, it = s.lipschitz()
     assert s2 == pytest.approx(s20, rel=1e-6)
     assert L == pytest.approx(L0, rel=1e-6)
