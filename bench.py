@@ -51,17 +51,22 @@ def kernel_hash() -> str:
 #   fp64       : read lam^{k-1}, lam^{k-2}, write lam^k, 8 bytes each                  -> 24
 #   mixed_fp32 : read H (4), l^{k-1} (4), l^{k-2} (4), write l^k (4)                    -> 16
 #   mixed_bf16 : read H (2), l^{k-1} (4), l^{k-2} (4), write l^k (4)                    -> 14
-# adaptive step (one trial pass per attempt: both iterates in, two candidates out)
-#   fp64       : read lam^k, lam^{k-1}, write two candidates, 8 bytes each             -> 32
-#   mixed_fp32 : read H (4), l^k (4), l^{k-1} (4), write two low-part candidates (8)   -> 20
-#   mixed_bf16 : read H (2), l^k (4), l^{k-1} (4), write two low-part candidates (8)   -> 18
+# adaptive step, dominant pass:
+#   fp64       : trial pass, read lam^k, lam^{k-1}, write two candidates, 8 bytes each      -> 32
+#   mixed_fp32 : re-forming trial pass, read H (4), l^{k-1} (4), l^{k-2} (4), write the
+#                re-formed l^k (4); the two candidates are not stored                     -> 16
+#   mixed_bf16 : the same with a BF16 H                                                   -> 14
+# (a retry pass of the split forms only reads: 12 / 10 bytes per pair)
 PASS_BYTES = {("constant", "fp64"): 24, ("constant", "mixed_fp32"): 16, ("constant", "mixed_bf16"): 14,
-              ("adaptive", "fp64"): 32, ("adaptive", "mixed_fp32"): 20, ("adaptive", "mixed_bf16"): 18}
+              ("adaptive", "fp64"): 32, ("adaptive", "mixed_fp32"): 16, ("adaptive", "mixed_bf16"): 14}
 _REP = {"fp64": "double,REP_F64", "mixed_fp32": "float,REP_SPLIT_F32", "mixed_bf16": "float,REP_SPLIT_BF16"}
 
 
 def pass_kernel(rule: str, precision: str) -> str:
-    mode = "PASS_TRIAL" if rule == "adaptive" else "PASS_STEP"
+    if rule == "adaptive":
+        mode = "PASS_TRIAL" if precision == "fp64" else "PASS_ADV"
+    else:
+        mode = "PASS_STEP"
     return f"pass_kernel<{_REP[precision]},{mode},MB=3>"
 
 
@@ -69,8 +74,14 @@ def step_kernel_stats(rep: dict, precision: str, rule: str) -> dict:
     """Dominant pass kernel of a fit (the phase with the larger total device time)."""
     low_iters = rep["iters_low"]
     hi_iters = rep["iters"] - rep["iters_low"]
-    # launches per accepted iteration: 1 for the constant step, trials / 2 / iters for the adaptive one
-    per_iter = (rep["trials"] / 2.0 / max(1, rep["iters"])) if rule == "adaptive" else 1.0
+    # launches per accepted iteration of the dominant kernel: 1 for the constant step; for the
+    # adaptive one trials / 2 / iters (FP64) or the re-forming passes per iteration (split forms)
+    if rule != "adaptive":
+        per_iter = 1.0
+    elif precision == "fp64":
+        per_iter = rep["trials"] / 2.0 / max(1, rep["iters"])
+    else:
+        per_iter = rep["adv_passes"] / max(1, rep["iters"])
     t_low = low_iters * rep["step_ms_low"]
     t_hi = hi_iters * rep["step_ms_fp64"]
     if precision != "fp64" and t_low >= t_hi and rep["step_samples_low"] > 0:
@@ -80,6 +91,12 @@ def step_kernel_stats(rep: dict, precision: str, rule: str) -> dict:
     return {"phase": "fp64", "ms": rep["step_ms_fp64"], "bytes_per_pair": PASS_BYTES[(rule, "fp64")],
             "launches": round(hi_iters * per_iter), "samples": rep["step_samples_fp64"],
             "kernel": pass_kernel(rule, "fp64")}
+
+
+def _contractions(rule: str, precision: str) -> int:
+    if rule != "adaptive":
+        return 2
+    return 3 if precision == "fp64" else 4
 
 
 def traffic_for(kernel: str) -> dict | None:
@@ -263,15 +280,17 @@ def main() -> int:
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "kernel": ks["kernel"], "avg_launch_ms": round(ks["ms"], 5), "sampled_launches": int(ks["samples"]),
                 "algorithmic_bytes_per_launch": alg_bytes, "launches_per_fit": ks["launches"],
-                # residual + adjoint contractions (2 flops per multiply-add each), twice for the trial pass
-                "mfma_tflops": round((6.0 if rule == "adaptive" else 4.0) * pairs * wl.n / (ks["ms"] * 1e-3) / 1e12, 2)
-                if ks["ms"] > 0 else 0.0}
+                # contractions (2 flops per multiply-add): residual + adjoint for the constant step,
+                # residual + two adjoints for the trial pass, plus the re-formed residual (split)
+                "mfma_tflops": round(_contractions(rule, args.precision) * 2.0 * pairs * wl.n
+                                     / (ks["ms"] * 1e-3) / 1e12, 2) if ks["ms"] > 0 else 0.0}
 
     extra = {
         "time_to_tol_s": [round(r["seconds"], 4) for r in reps],
         "iters": [r["iters"] for r in reps],
         "iters_low_precision": [r["iters_low"] for r in reps],
         "trial_passes": [int(r["trials"] / 2) for r in reps] if rule == "adaptive" else None,
+        "reforming_passes": [int(r["adv_passes"]) for r in reps],
         "restarts": [int(r["restarts"]) for r in reps],
         "step_final_over_L": last["step_final"] / last["L"],
         "kkt_final": last["kkt"],

@@ -115,9 +115,10 @@ typedef struct {
     double cert_primal;
     double cert_gap;
     double y_err_bound;
-    /* Device time of the fused pair pass (one launch per iteration), from HIP events recorded
-       on the solver's stream around one launch per stopping-test interval: average ms per
-       launch and number of sampled launches, for the low-precision and the FP64 phase. */
+    /* Device time of the dominant fused pair pass, from HIP events recorded on the solver's
+       stream: the constant step's pass, the FP64 adaptive step's trial pass, or the split forms'
+       re-forming trial pass.  Average ms per launch and number of sampled launches, for the
+       low-precision and the FP64 phase. */
     double step_ms_low;
     double step_ms_fp64;
     double step_samples_low;
@@ -127,6 +128,8 @@ typedef struct {
     double step_final;
     double trials;
     double restarts;         /* momentum restarts taken (options.restart) */
+    double adv_passes;       /* split forms, adaptive step: trial passes that also re-formed and
+                                stored the previous accepted iterate (the rest only read) */
 } cr_report;
 
 /* Fills *opt with the defaults listed above. */

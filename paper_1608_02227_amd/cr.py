@@ -75,6 +75,7 @@ class CRReport(C.Structure):
         ("step_final", C.c_double),
         ("trials", C.c_double),
         ("restarts", C.c_double),
+        ("adv_passes", C.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -24,11 +24,12 @@ LamRep rep_of(int precision) {
     return precision == CR_FP64 ? REP_F64 : (precision == CR_MIXED_FP32 ? REP_SPLIT_F32 : REP_SPLIT_BF16);
 }
 
-// bytes of the multiplier state per (padded) pair: two iterates plus, for the adaptive step, two
-// candidate buffers (the split forms add the shared high part)
+// bytes of the multiplier state per (padded) pair
 size_t state_bytes_per_pair(LamRep r, bool adaptive) {
-    const size_t iterates = adaptive ? 4 : 2;
-    return r == REP_F64 ? 8 * iterates : 4 * iterates + (r == REP_SPLIT_F32 ? 4 : 2);
+    // FP64 adaptive: two iterates + two stored candidates; split forms re-form the accepted
+    // candidate instead of storing it
+    if (r == REP_F64) return adaptive ? 32 : 16;
+    return 8 + (r == REP_SPLIT_F32 ? 4 : 2);
 }
 
 bool all_finite(const double *p, size_t n) {
@@ -216,7 +217,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
 #define CR_ALLOC(ptr, bytes) do { int r_ = s->alloc((void **)&(ptr), (bytes)); if (r_) return bail(r_); } while (0)
     CR_ALLOC(s->lam[0], lamsz);
     CR_ALLOC(s->lam[1], lamsz);
-    if (s->adaptive) {
+    if (s->adaptive && s->rep == REP_F64) {
         CR_ALLOC(s->lam[2], lamsz);
         CR_ALLOC(s->lam[3], lamsz);
     }
@@ -260,6 +261,14 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         CR_ALLOC(s->y32, nr * 4);
         CR_ALLOC(s->xi32, rows_np * 4);
         CR_ALLOC(s->dmy32, nr * 4);
+    }
+    if (s->deferred()) {
+        CR_ALLOC(s->yo64, nr * 8);
+        CR_ALLOC(s->xio64, rows_np * 8);
+        CR_ALLOC(s->dmyo64, nr * 8);
+        CR_ALLOC(s->yo32, nr * 4);
+        CR_ALLOC(s->xio32, rows_np * 4);
+        CR_ALLOC(s->dmyo32, nr * 4);
     }
     double *dx = nullptr, *dyb = nullptr, *dmu = nullptr;
     CR_ALLOC(dx, hx.size() * 8);
@@ -361,6 +370,8 @@ int cr_solver::adjoint_to(int idx, double *y, double *xi, double *dmy, bool with
 // Split representations: fold lam^k's low part into the shared high part (H <- round(H + l_k)),
 // re-express both low parts against it and cache the FP64 adjoint C^T H for the next steps.
 int cr_solver::rebase() {
+    int rc = materialize();
+    if (rc) return rc;
     if (rep == REP_F64) return CR_OK;
     PassArgs a{};
     a.lam_h = lam_hi;
@@ -434,6 +445,27 @@ int cr_solver::refresh_eta(bool have_cur_in_yc) {
     return CR_OK;
 }
 
+// Store the accepted candidate of the last trial (split forms with the adaptive step): one
+// constant-step-form pass from lam[cur], lam[prv] with the accepted step and that trial's pass
+// arrays writes lam^k over lam[prv].
+int cr_solver::materialize() {
+    if (!pend) return CR_OK;
+    PassArgs a{};
+    a.lam_h = lam_hi;
+    a.lam_a = lam[cur];
+    a.lam_b = lam[prv];
+    a.beta_prev = pend_beta;
+    a.beta_next = 0.0;
+    a.inv_L = pend_invs;
+    a.xhat = xhat32; a.xi = xio32; a.yv = yo32; a.dmy = dmyo32;
+    a.part_acc = part_acc;
+    a.part_col = part_col;
+    CR_HIP(launch_pass(g, PASS_STEP, true, rep, a, stream));
+    std::swap(cur, prv);
+    pend = false;
+    return CR_OK;
+}
+
 // One iteration under the adaptive rule of eq. "eq:adaptive-check" (s_0 = L, s_k = s_{k-1}
 // upsilon^(l_k - 1), smallest admissible l_k >= 0).  Each fused trial pass evaluates two consecutive
 // candidates l and l + 1 from one read of the iterates.  With every pair dualized the dual function
@@ -450,14 +482,25 @@ int cr_solver::step_adaptive() {
     int accepted = -1;
     double s_new = s_step;
     bool restart_now = false;
+    const bool defer = deferred();
     for (int attempt = 0; attempt < 64; ++attempt) {
+        // split forms: the first attempt also re-forms and stores the previous accepted iterate
+        const bool adv = defer && pend;
         PassArgs a{};
         a.lam_h = lam_hi;
         a.lam_a = lam[cur];
         a.lam_b = lam[prv];
-        a.lam_c = lam[fa];
-        a.lam_d = lam[fb];
+        if (!defer) {
+            a.lam_c = lam[fa];
+            a.lam_d = lam[fb];
+        }
         a.beta_prev = bk;
+        if (adv) {
+            a.beta_prev = pend_beta;
+            a.inv_Lo = pend_invs;
+            a.beta_next = bk;
+            a.xi_o = xio32; a.yv_o = yo32; a.dmy_o = dmyo32;
+        }
         a.inv_L = 1.0 / sa;
         a.inv_L2 = 1.0 / sb;
         a.part_acc = part_acc;
@@ -470,13 +513,20 @@ int cr_solver::step_adaptive() {
         } else {
             a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
         }
-        const bool timed = !ev_pending;
+        // the timed launches are the dominant kind: re-forming trials (split) or storing trials
+        const bool timed = !ev_pending && (adv || !defer);
         if (timed) CR_HIP(hipEventRecord(ev_a, stream));
-        CR_HIP(launch_pass(g, PASS_TRIAL, fp32pass, rep, a, stream));
+        CR_HIP(launch_pass(g, adv ? PASS_ADV : (defer ? PASS_TRIAL_NS : PASS_TRIAL), fp32pass, rep, a, stream));
         if (timed) {
             CR_HIP(hipEventRecord(ev_b, stream));
             ev_pending = true;
             ev_pending_low = fp32pass;
+        }
+        if (adv) {
+            // lam^k now sits in lam[prv]: it becomes the current iterate
+            std::swap(cur, prv);
+            pend = false;
+            adv_passes += 1.0;
         }
         TrialFinalizeArgs f{};
         f.part_acc[0] = part_acc; f.part_acc[1] = part_acc2;
@@ -502,9 +552,16 @@ int cr_solver::step_adaptive() {
         sb = sa * upsilon;
     }
     if (accepted < 0) return CR_ENUMERIC;   // no admissible step after 2^128-fold growth
-    const int c = cur, p = prv, A = fa, B = fb;
-    if (accepted == 0) { cur = A; prv = c; fa = p; fb = B; }
-    else { cur = B; prv = c; fa = A; fb = p; }
+    if (defer) {
+        // the accepted candidate is re-formed by the next pass from lam[cur], lam[prv]
+        pend = true;
+        pend_beta = bk;
+        pend_invs = 1.0 / s_new;
+    } else {
+        const int c = cur, p = prv, A = fa, B = fb;
+        if (accepted == 0) { cur = A; prv = c; fa = p; fb = B; }
+        else { cur = B; prv = c; fa = A; fb = p; }
+    }
     // optional gradient restart: the accepted step points against the iterate's own movement
     if (opt.restart && restart_now) {
         t = 1.0;
@@ -515,9 +572,15 @@ int cr_solver::step_adaptive() {
     // eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta) into the slot of eta(lam^{k-1}),
     // and the pass arrays (1 + beta_k) eta(lam^{k+1}) - beta_k eta(lam^k) for the next iteration
     const int en = 1 - ecur;
-    CR_HIP(launch_accept(g, y64, xi64, dmy64, uD[accepted], wD[accepted], ye[ecur], xie[ecur], ye[en], xie[en],
-                         dmye[en], fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr, fp32pass ? dmy32 : nullptr,
-                         xhat64, 1.0 / delta, beta_k, stream));
+    if (defer) {
+        // keep this trial's pass arrays for re-forming its candidate; the next ones go to the others
+        std::swap(y64, yo64); std::swap(xi64, xio64); std::swap(dmy64, dmyo64);
+        std::swap(y32, yo32); std::swap(xi32, xio32); std::swap(dmy32, dmyo32);
+    }
+    const double *yt = defer ? yo64 : y64, *xit = defer ? xio64 : xi64;
+    CR_HIP(launch_accept(g, yt, xit, y64, xi64, dmy64, uD[accepted], wD[accepted], ye[ecur], xie[ecur], ye[en],
+                         xie[en], dmye[en], fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr,
+                         fp32pass ? dmy32 : nullptr, xhat64, 1.0 / delta, beta_k, stream));
     ecur = en;
     t = t_next;
     beta_last = beta_k;
@@ -592,24 +655,33 @@ void cr_solver::collect_timing() {
 int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
     const double t0 = now_s();
     CR_HIP(hipSetDevice(device));
-    CR_HIP(launch_power_init(g, xhat64, y64, xi64, dmy64, stream));
     // The constant step 1/L needs L itself; the adaptive rule only starts from s_0 = L and checks
     // every step, so a coarser estimate serves it.
     const double rtol = opt.power_rtol > 0.0 ? opt.power_rtol : (adaptive ? 1e-4 : 1e-8);
+    // Mixed modes run the power passes in FP32 when the tolerance is far above FP32 resolution
+    // (the FP64 vector is normalized each step and re-rounded, so errors do not accumulate).
+    const bool f32 = fp32pass && rtol >= 1e-6;
+    CR_HIP(launch_power_init(g, xhat64, y64, xi64, dmy64, f32 ? y32 : nullptr, f32 ? xi32 : nullptr,
+                             f32 ? dmy32 : nullptr, stream));
     double est = 0.0;
     int it = 0;
     for (it = 1; it <= opt.power_max_iters; ++it) {
         PassArgs a{};
-        a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
+        if (f32) {
+            a.xhat = xhat32; a.xi = xi32; a.yv = y32; a.dmy = dmy32;
+        } else {
+            a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
+        }
         a.part_acc = part_acc; a.part_col = part_col; a.part_red = part_red;
-        CR_HIP(launch_pass(g, PASS_POWER, false, REP_F64, a, stream));
+        CR_HIP(launch_pass(g, PASS_POWER, f32, REP_F64, a, stream));
         FinalizeArgs f{};
         f.part_acc = part_acc; f.part_col = part_col; f.xf = xhat64; f.ybar = ybar64;
         f.y = y64; f.xi = xi64; f.dmy = dmy64; f.rowred = rowred; f.inv_delta = 1.0; f.power = 1;
-        CR_HIP(launch_finalize(g, false, f, stream));
+        CR_HIP(launch_finalize(g, f32, f, stream));
         CR_HIP(launch_reduce(part_red, g.grid(), kRed, 0, 1, scal, stream));
         CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 1, stream));
-        CR_HIP(launch_normalize(g, y64, xi64, dmy64, scal + 1, stream));
+        CR_HIP(launch_normalize(g, y64, xi64, dmy64, f32 ? y32 : nullptr, f32 ? xi32 : nullptr,
+                                f32 ? dmy32 : nullptr, scal + 1, stream));
         CR_HIP(hipMemcpyAsync(h_scal, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
         CR_HIP(hipStreamSynchronize(stream));
         const double nw = h_scal[0];
@@ -692,6 +764,7 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
     rep_out->step_final = adaptive ? s_step : L;
     rep_out->trials = trials;
     rep_out->restarts = restarts;
+    rep_out->adv_passes = adv_passes;
     rep_out->step_ms_fp64 = step_n[1] > 0 ? step_ms_sum[1] / step_n[1] : 0.0;
     bool finite = true;
     for (int q = 0; q < nsc; ++q) finite = finite && std::isfinite(h_scal[q]);
@@ -703,6 +776,8 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
 int cr_solver::promote() {
     if (rep == REP_F64) return CR_OK;
     CR_HIP(hipSetDevice(device));
+    int rc0 = materialize();
+    if (rc0) return rc0;
     const size_t bytes = (size_t)g.Nr * g.ld * 8;
     const int nbuf = adaptive ? 4 : 2;
     void *nb[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -842,6 +917,8 @@ extern "C" int64_t cr_solver_iterations(const cr_solver *s) { return s ? s->k : 
 extern "C" int cr_solver_get_lambda(cr_solver *s, double *lambda) {
     if (!s || !lambda) return CR_EINVAL;
     CR_HIP(hipSetDevice(s->device));
+    int rc0 = s->materialize();
+    if (rc0) return rc0;
     double *d = nullptr;
     const size_t bytes = (size_t)s->g.N * s->g.N * 8;
     int rc = s->alloc((void **)&d, bytes);
@@ -857,6 +934,8 @@ extern "C" int cr_solver_get_lambda(cr_solver *s, double *lambda) {
 extern "C" int cr_solver_get_lambda_rows(cr_solver *s, int64_t row0, int64_t nrows, double *rows) {
     if (!s || !rows || row0 < 0 || nrows < 1 || row0 + nrows > s->g.N) return CR_EINVAL;
     CR_HIP(hipSetDevice(s->device));
+    int rc0 = s->materialize();
+    if (rc0) return rc0;
     double *d = nullptr;
     const size_t bytes = (size_t)nrows * s->g.N * 8;
     int rc = s->alloc((void **)&d, bytes);
@@ -896,7 +975,9 @@ static int primal_out(cr_solver *s, const double *ysrc, const double *xisrc, dou
 extern "C" int cr_solver_get_primal(cr_solver *s, double *y, double *xi) {
     if (!s || !y || !xi) return CR_EINVAL;
     CR_HIP(hipSetDevice(s->device));
-    int rc = s->adjoint_to(s->cur, s->yc, s->xic, s->dmyc, false, nullptr, nullptr, nullptr);
+    int rc = s->materialize();
+    if (rc) return rc;
+    rc = s->adjoint_to(s->cur, s->yc, s->xic, s->dmyc, false, nullptr, nullptr, nullptr);
     if (rc) return rc;
     return primal_out(s, s->yc, s->xic, y, xi, false);
 }
@@ -957,6 +1038,8 @@ static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, d
     rc = primal_out(s, s->yc, s->xic, y, xi, dev);
     if (rc) { delete s; return rc; }
     if (lambda) {
+        rc = s->materialize();
+        if (rc) { delete s; return rc; }
         if (dev) {
             if (launch_unpack_lambda(s->g, s->rep, s->rep == REP_F64 ? s->lam[s->cur] : s->lam_hi,
                                      (const float *)s->lam[s->cur], lambda, s->stream) != hipSuccess ||

@@ -28,6 +28,16 @@ struct cr_solver {
     double *xhat64 = nullptr, *ybar64 = nullptr;
     double *y64 = nullptr, *xi64 = nullptr, *dmy64 = nullptr;      // eta^{k+1} for the next step
     float *xhat32 = nullptr, *y32 = nullptr, *xi32 = nullptr, *dmy32 = nullptr;
+    // Split forms with the adaptive step: the accepted candidate is not stored by its trial pass;
+    // the next pass re-forms it from the two stored iterates, the accepted step and the pass
+    // arrays of that trial, kept here (swapped with the current ones at each acceptance).
+    double *yo64 = nullptr, *xio64 = nullptr, *dmyo64 = nullptr;
+    float *yo32 = nullptr, *xio32 = nullptr, *dmyo32 = nullptr;
+    bool pend = false;          // an accepted iterate lam^k is not yet stored
+    double pend_beta = 0.0;     // its lam~ = lam[cur] + pend_beta (lam[cur] - lam[prv])
+    double pend_invs = 0.0;     // and its step 1 / s_k
+    double adv_passes = 0.0;    // re-forming trial passes launched
+    bool deferred() const { return adaptive && rep != cr::REP_F64; }
     double *yc = nullptr, *xic = nullptr, *dmyc = nullptr;         // eta(lam^k) for tests/output
     double *yr = nullptr, *xir = nullptr, *dmyr = nullptr;         // scratch primal (repair, prime)
     double *rowred = nullptr;
@@ -77,6 +87,7 @@ struct cr_solver {
     int step_once();
     int step_adaptive();
     int refresh_eta(bool have_cur_in_yc);
+    int materialize();
     int lipschitz(double *L, double *s2, int32_t *it);
     int check(cr_report *rep, bool certificate);
     int promote();

@@ -26,9 +26,16 @@ enum PassMode : int {
     PASS_RESID = 5,  // writes s = C eta (FP64, zero diagonal and padding) into lam_b
     PASS_REBASE = 6, // split forms: H <- round(H + l_k), both low parts re-expressed against the
                      // new H, and the FP64 adjoint of the new H (cached for the next steps)
-    PASS_TRIAL = 7   // adaptive step: two Step-2 candidates lam~ - s / s_a and lam~ - s / s_b from
+    PASS_TRIAL = 7,  // adaptive step: two Step-2 candidates lam~ - s / s_a and lam~ - s / s_b from
                      // one read of the iterates, written to lam_c / lam_d, with the adjoints of
-                     // D = candidate - lam~ (part_acc / part_acc2) and ||D||^2 (part_red slots 0, 1)
+                     // D = candidate - lam~ (part_acc / part_acc2), ||D||^2 (part_red slots 0, 1)
+                     // and <D, candidate - lam^k> (slots 2, 3)
+    PASS_TRIAL_NS = 8, // PASS_TRIAL without storing the candidates (split forms; the accepted one
+                       // is re-formed by the next PASS_ADV)
+    PASS_ADV = 9     // split forms: first re-form the accepted candidate of the previous trial,
+                     // lam^k = (lam~^k - s(eta~^k) / s_k)_+ from lam_a = lam^{k-1}, lam_b = lam^{k-2},
+                     // beta_prev, inv_Lo and the previous pass arrays (xi_o, yv_o, dmy_o), store it
+                     // over lam_b, then run PASS_TRIAL_NS from (lam^k, lam^{k-1}) with beta_next
 };
 
 // Tiling shared by host and device code.
@@ -99,6 +106,11 @@ struct PassArgs {
     double inv_L2;      // 1 / s_b
     void *part_acc2;    // adjoint partials of candidate b's difference
     void *part_col2;
+    // PASS_ADV only: pass arrays of the previous trial and its accepted step
+    const void *xi_o;
+    const void *yv_o;
+    const void *dmy_o;
+    double inv_Lo;      // 1 / s_k of the accepted candidate being re-formed
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,
@@ -143,21 +155,22 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
 hipError_t launch_reduce2(const double *pa, int ba, int sa, int na, const double *pb, int bb, int sb, int nb,
                           double *out, hipStream_t st);
 
-// Accepted adaptive step: eta(lam^{k+1}) from eta(lam~^{k+1}) (in y, xi) and the adjoint of D,
-// then the next pass arrays (1 + beta) eta(lam^{k+1}) - beta eta(lam^k).
-hipError_t launch_accept(const Geometry &g, double *y, double *xi, double *dmy, const double *uD, const double *wD,
-                         const double *yk, const double *xik, double *ye, double *xie, double *dmye, float *y32,
-                         float *xi32, float *dmy32, const double *xhat64, double inv_delta, double beta,
-                         hipStream_t st);
+// Accepted adaptive step: eta(lam^{k+1}) from eta(lam~^{k+1}) (yt, xit) and the adjoint of D,
+// then the next pass arrays (1 + beta) eta(lam^{k+1}) - beta eta(lam^k) into (y, xi, dmy).
+hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit, double *y, double *xi, double *dmy,
+                         const double *uD, const double *wD, const double *yk, const double *xik, double *ye,
+                         double *xie, double *dmye, float *y32, float *xi32, float *dmy32, const double *xhat64,
+                         double inv_delta, double beta, hipStream_t st);
 
 // Sums / maxima of per-block partials: out[q] = op_q over blocks of part[b * stride + q],
 // with op = max for q < nmax and sum otherwise.  Single workgroup, deterministic order.
 hipError_t launch_reduce(const double *part, int blocks, int stride, int nmax, int nout,
                          double *out, hipStream_t st);
 
-// Multiplies y, xi, dmy (FP64, Nr / Nr x NP / Nr) by 1/sqrt(sq[0] + sq[1]).
-hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dmy,
-                            const double *sq, hipStream_t st);
+// Multiplies y, xi, dmy (FP64, Nr / Nr x NP / Nr) by 1/sqrt(sq[0] + sq[1]); optional FP32 copies
+// of the result (all three null or all three set).
+hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dmy, float *y32, float *xi32,
+                            float *dmy32, const double *sq, hipStream_t st);
 
 // FP64 multipliers (Nr x ld) from a split representation: dst = H + lo.
 hipError_t launch_merge(const Geometry &g, LamRep rep, const void *hi, const float *lo, double *dst,
@@ -181,9 +194,10 @@ hipError_t launch_prepare(const Geometry &g, const double *x, const double *ybar
                           hipStream_t st);
 
 // Power-iteration start: v_y,l = -1 + 2 l / (N - 1), v_xi = 1, scaled by 1/||v||; writes
-// y, xi and dmy = xi^T x - y (FP64, padded) from xhat64.
+// y, xi and dmy = xi^T x - y (FP64, padded) from xhat64, plus optional FP32 copies (all three
+// null or all three set).
 hipError_t launch_power_init(const Geometry &g, const double *xhat64, double *y, double *xi,
-                             double *dmy, hipStream_t st);
+                             double *dmy, float *y32, float *xi32, float *dmy32, hipStream_t st);
 
 // Pads dense FP64 y (N) and xi (N x n) into Nr / Nr x NP arrays and sets dmy = xi^T x - y.
 hipError_t launch_pad_primal(const Geometry &g, const double *y_in, const double *xi_in,

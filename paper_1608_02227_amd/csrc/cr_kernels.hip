@@ -41,6 +41,19 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 MFMA with K = 32: lane l holds A[l % 16][8 (l / 16) + q] and B[8 (l / 16) + q][l % 16],
+// q < 8, and receives C[4 (l / 16) + v][l % 16], v < 4 (the output layout of the FP32 16x16x4 form).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4 mfma16_bf16(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// x = hi + lo + O(2^-16 |x|) with hi, lo in BF16; a product of two such splits taken as
+// hi*hi + hi*lo + lo*hi (three BF16 MFMAs, FP32 accumulation) has relative error ~3 * 2^-16.
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
 // ---- multiplier storage -------------------------------------------------------------------
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 // Round-to-nearest-even of a finite float to BF16.
@@ -132,9 +145,18 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     constexpr int TW = 4 * CPL;                      // tile width (columns)
     constexpr int TPS = kSuper / TW;                 // tiles per super tile
     constexpr bool kSplit = (REP != REP_F64);
-    constexpr bool kTrial = (MODE == PASS_TRIAL);
+    constexpr bool kAdv = (MODE == PASS_ADV);
+    constexpr bool kStoreCand = (MODE == PASS_TRIAL);
+    constexpr bool kTrial = (MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS || kAdv);
+    static_assert(!(kAdv && REP == REP_F64), "the re-forming trial pass is built for the split forms");
     constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER || MODE == PASS_REBASE ||
                                kTrial);
+    // Split-form trial passes take the two adjoints of the candidate differences D on BF16 MFMA with
+    // split operands (D and Xhat each as hi + lo BF16; three products per pair of operands): D only
+    // enters the step test and the update eta(lam~) + C^T D, where ~1e-5 relative error is harmless,
+    // and the FP32 form's cost would make these passes compute-bound.  The residual stays FP32.
+    constexpr bool kBfAdj = kTrial && kSplit;
+    constexpr int XTS = kSuper + 8;                  // BF16 transposed tile: row stride (elements)
     constexpr bool kResidual = (MODE != PASS_ADJ && MODE != PASS_REBASE);
     constexpr bool kColRed = kAdjoint || MODE == PASS_REPAIR;
     constexpr bool kReadA = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT || MODE == PASS_REBASE ||
@@ -146,6 +168,10 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
 
     __shared__ T sX[2 * BUF];
     __shared__ T sY[2 * kSuper];
+    __shared__ T sYo[kAdv ? 2 * kSuper : 1];
+    // transposed BF16 hi / lo copies of the staged Xhat tile (feature-major), for the BF16 adjoint
+    __shared__ __attribute__((aligned(16))) __bf16 sXTh[kBfAdj ? 2 * NP * XTS : 8];
+    __shared__ __attribute__((aligned(16))) __bf16 sXTl[kBfAdj ? 2 * NP * XTS : 8];
     __shared__ T sCol[kColRed ? 2 * kWaves * kSuper : 1];
     __shared__ T sCol2[kTrial ? 2 * kWaves * kSuper : 1];
     __shared__ int sArg[MODE == PASS_REPAIR ? 2 * kWaves * kSuper : 1];
@@ -166,6 +192,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     const int cend = min(g.ld, cbeg + g.chunk_cols);
     const int nsup = (cend - cbeg) / kSuper;
     const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L, invL2 = (T)a.inv_L2;
+    const T invLo = (T)a.inv_Lo;
     // Output rows of the 16x16x4 MFMA: lane group g, item v receives row 4 g + v in the FP32 form
     // and row 4 v + g in the FP64 form.  A-row rho is therefore fed the source that lane group
     // g(rho), item v(rho) must see: feature 16 mb + 4 g + v in the adjoint contraction, column
@@ -181,6 +208,14 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     for (int s = 0; s < 4 * MB; ++s)
         bxi[s] = kResidual ? xi[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmy_i = kResidual ? dmy[i] : (T)0;
+    // PASS_ADV: the previous trial's row operands (re-forming its accepted candidate)
+    const T *xio = static_cast<const T *>(a.xi_o);
+    const T *yvo = static_cast<const T *>(a.yv_o);
+    T bxio[kAdv ? 4 * MB : 1];
+#pragma unroll
+    for (int s = 0; s < (kAdv ? 4 * MB : 1); ++s)
+        bxio[s] = kAdv ? xio[(size_t)i * NP + 4 * s + lq] : (T)0;
+    const T dmyo_i = kAdv ? static_cast<const T *>(a.dmy_o)[i] : (T)0;
 
     V4 acc[MB];
     V4 acc2[kTrial ? MB : 1];
@@ -222,9 +257,12 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     if (nsup > 0) {
         for (int e = tid; e < kSuper * NP; e += NT) {
             const int jj = e / NP, m = e - jj * NP;
-            sX[jj * SX + m] = xhat[(size_t)(cbeg + jj) * NP + m];
+            const T v = xhat[(size_t)(cbeg + jj) * NP + m];
+            sX[jj * SX + m] = v;
+            if constexpr (kBfAdj) split_bf16((float)v, sXTh[m * XTS + jj], sXTl[m * XTS + jj]);
         }
         if (tid < kSuper) sY[tid] = kResidual ? yv[cbeg + tid] : (T)0;
+        if (kAdv && tid < kSuper) sYo[tid] = yvo[cbeg + tid];
     }
     static_assert(TPS % 2 == 0, "the two-deep prefetch ring needs an even number of tiles per super tile");
     Raw<REP> pf[2];
@@ -248,6 +286,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
 #pragma unroll
         for (int q = 0; q < XR; ++q) xr[q] = xhat[(size_t)cnx * NP + tid + q * NT];
         const T yr = kResidual ? yv[cnx + (tid & (kSuper - 1))] : (T)0;
+        const T yro = kAdv ? yvo[cnx + (tid & (kSuper - 1))] : (T)0;
         __builtin_amdgcn_sched_barrier(0);
 
 #pragma unroll
@@ -267,18 +306,24 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             __builtin_amdgcn_sched_barrier(0);
 
             V4 S[NB];
+            V4 So[kAdv ? NB : 1];
 #pragma unroll
             for (int bb = 0; bb < NB; ++bb) {
                 S[bb] = V4{0, 0, 0, 0};
+                if (kAdv) So[bb] = V4{0, 0, 0, 0};
                 if (kResidual) {
                     // all 4 MB steps: Xi is zero beyond column n - 1, so the padded steps add zero
                     // and the loop carries no branch (which would make the compiler drain the
                     // prefetch queue at every join)
 #pragma unroll
-                    for (int s = 0; s < 4 * MB; ++s)
-                        S[bb] = mfma16(sXb[(jl + acol + 4 * bb) * SX + 4 * s + lq], bxi[s], S[bb]);
+                    for (int s = 0; s < 4 * MB; ++s) {
+                        const T xa = sXb[(jl + acol + 4 * bb) * SX + 4 * s + lq];
+                        S[bb] = mfma16(xa, bxi[s], S[bb]);
+                        if constexpr (kAdv) So[bb] = mfma16(xa, bxio[s], So[bb]);
+                    }
                 }
             }
+            const T *sYob = sYo + (kAdv ? b * kSuper : 0);
 
             T out[CPL];
             T out2[kTrial ? CPL : 1];
@@ -289,6 +334,8 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             const int i0w = strip * kRows + w * 16;
             const int jt0 = cst + jl;
             const bool interior = (i0w + 16 <= g.N) && (jt0 + TW <= g.N) && (i0w + 16 <= jt0 || jt0 + TW <= i0w);
+            // split forms: trial sums of this tile in FP32, folded into the FP64 totals once per tile
+            T tr0 = (T)0, tr1 = (T)0, tr2 = (T)0, tr3 = (T)0;
             auto epilogue = [&](auto masked) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
@@ -326,11 +373,32 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     cand_b[c] = tb;
                     out[c] = ok ? ta - lt : (T)0;                        // D_a
                     out2[c] = ok ? tb - lt : (T)0;                       // D_b
-                    red0 += (double)out[c] * (double)out[c];
-                    red1 += (double)out2[c] * (double)out2[c];
-                    red2 += (double)out[c] * (double)(ta - P);           // <D_a, cand_a - lam^k>
-                    red3 += (double)out2[c] * (double)(tb - P);
-                } else if constexpr (MODE == PASS_TRIAL) {
+                    red0 += out[c] * out[c];
+                    red1 += out2[c] * out2[c];
+                    red2 += out[c] * (ta - P);                           // <D_a, cand_a - lam^k>
+                    red3 += out2[c] * (tb - P);
+                } else if constexpr (kAdv) {
+                    const T H = (T)hi_at<REP>(cur, c);
+                    const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
+                    // re-form the accepted candidate of the previous trial: lam^k (low part)
+                    const T lto = l1 + bp * (l1 - l2);
+                    const T so = (sYob[jc + c] + dmyo_i) - So[c >> 2][c & 3];
+                    T z = fmax(lto - so * invLo, -H);
+                    z = ok ? z : (T)0;
+                    cur.b[c >> 2][c & 3] = (float)z;                     // stored over lam^{k-2}
+                    // trial from (lam^k, lam^{k-1})
+                    const T lt = z + bn * (z - l1);
+                    T la = fmax(lt - s * invL, -H);
+                    T lb = fmax(lt - s * invL2, -H);
+                    la = ok ? la : (T)0;
+                    lb = ok ? lb : (T)0;
+                    out[c] = ok ? la - lt : (T)0;
+                    out2[c] = ok ? lb - lt : (T)0;
+                    tr0 += out[c] * out[c];
+                    tr1 += out2[c] * out2[c];
+                    tr2 += out[c] * (la - z);                            // <D_a, cand_a - lam^k>
+                    tr3 += out2[c] * (lb - z);
+                } else if constexpr (MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS) {
                     const T H = (T)hi_at<REP>(cur, c);
                     const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
                     const T lt = l1 + bp * (l1 - l2);                    // low part of lam~^k
@@ -342,10 +410,10 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     cand_b[c] = lb;
                     out[c] = ok ? la - lt : (T)0;
                     out2[c] = ok ? lb - lt : (T)0;
-                    red0 += (double)out[c] * (double)out[c];
-                    red1 += (double)out2[c] * (double)out2[c];
-                    red2 += (double)out[c] * (double)(la - l1);          // <D_a, cand_a - lam^k>
-                    red3 += (double)out2[c] * (double)(lb - l1);
+                    tr0 += out[c] * out[c];
+                    tr1 += out2[c] * out2[c];
+                    tr2 += out[c] * (la - l1);                           // <D_a, cand_a - lam^k>
+                    tr3 += out2[c] * (lb - l1);
                 } else if constexpr (MODE == PASS_ADJ) {
                     T v;
                     if constexpr (REP == REP_F64) v = (T)cur.p[c];
@@ -390,9 +458,15 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             };
             if (interior) epilogue(std::false_type{});
             else epilogue(std::true_type{});
+            if constexpr (kTrial && kSplit) {
+                red0 += (double)tr0;
+                red1 += (double)tr1;
+                red2 += (double)tr2;
+                red3 += (double)tr3;
+            }
             {
                 const size_t e = rowoff + j0;
-                if constexpr (kTrial) {
+                if constexpr (kStoreCand) {
                     if constexpr (REP == REP_F64) {
                         *reinterpret_cast<d4 *>(pc64 + e) = d4{(double)cand_a[0], (double)cand_a[1],
                                                                (double)cand_a[2], (double)cand_a[3]};
@@ -407,7 +481,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 } else if constexpr (REP == REP_F64) {
                     if (MODE == PASS_STEP || MODE == PASS_RESID) *reinterpret_cast<d4 *>(pb64 + e) = cur.q;
                 } else {
-                    if (MODE == PASS_STEP || MODE == PASS_REBASE) {
+                    if (MODE == PASS_STEP || MODE == PASS_REBASE || kAdv) {
                         *reinterpret_cast<f4 *>(pb32 + e) = cur.b[0];
                         *reinterpret_cast<f4 *>(pb32 + e + 4) = cur.b[1];
                     }
@@ -424,12 +498,45 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 }
             }
 
+            if constexpr (kBfAdj) {
+                static_assert(CPL == 8, "the BF16 adjoint takes a lane's 8 consecutive columns as its K slice");
+                // A[m][k] = Xhat[column jl + 8 lq + k][feature 16 mb + lr]; B[k][n] = D[row lr][column
+                // jl + 8 lq + k]
+                bf8 dh, dl, eh, el;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    __bf16 h, lo;
+                    split_bf16((float)out[c], h, lo);
+                    dh[c] = h; dl[c] = lo;
+                    split_bf16((float)out2[c], h, lo);
+                    eh[c] = h; el[c] = lo;
+                }
+                const __bf16 *xth = sXTh + b * NP * XTS + jl + 8 * lq;
+                const __bf16 *xtl = sXTl + b * NP * XTS + jl + 8 * lq;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    const bf8 ah = *reinterpret_cast<const bf8 *>(xth + (16 * mb + lr) * XTS);
+                    const bf8 al = *reinterpret_cast<const bf8 *>(xtl + (16 * mb + lr) * XTS);
+                    f4 x = *reinterpret_cast<f4 *>(&acc[mb]);
+                    x = mfma16_bf16(ah, dh, x);
+                    x = mfma16_bf16(ah, dl, x);
+                    x = mfma16_bf16(al, dh, x);
+                    acc[mb] = *reinterpret_cast<V4 *>(&x);
+                    f4 z = *reinterpret_cast<f4 *>(&acc2[mb]);
+                    z = mfma16_bf16(ah, eh, z);
+                    z = mfma16_bf16(ah, el, z);
+                    z = mfma16_bf16(al, eh, z);
+                    acc2[mb] = *reinterpret_cast<V4 *>(&z);
+                }
+            }
             if (kAdjoint) {
+                if constexpr (!kBfAdj) {
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
+                    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c)
-                        acc[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out[c], acc[mb]);
+                        for (int c = 0; c < CPL; ++c)
+                            acc[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out[c], acc[mb]);
+                }
                 T cs[CPL];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) cs[c] = row16_sum(out[c]);
@@ -438,11 +545,13 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     for (int c = 0; c < CPL; ++c) sCol[(b * kWaves + w) * kSuper + jc + c] = cs[c];
                 }
                 if constexpr (kTrial) {
+                    if constexpr (!kBfAdj) {
 #pragma unroll
-                    for (int mb = 0; mb < MB; ++mb)
+                        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                        for (int c = 0; c < CPL; ++c)
-                            acc2[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out2[c], acc2[mb]);
+                            for (int c = 0; c < CPL; ++c)
+                                acc2[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out2[c], acc2[mb]);
+                    }
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) cs[c] = row16_sum(out2[c]);
                     if (lr == 15) {
@@ -482,8 +591,13 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 const int e = tid + q * NT;
                 const int jj = e / NP, m = e - jj * NP;
                 sXn[jj * SX + m] = xr[q];
+                if constexpr (kBfAdj) {
+                    const int o = (b ^ 1) * NP * XTS + m * XTS + jj;
+                    split_bf16((float)xr[q], sXTh[o], sXTl[o]);
+                }
             }
             if (tid < kSuper) sY[(b ^ 1) * kSuper + tid] = yr;
+            if (kAdv && tid < kSuper) sYo[(b ^ 1) * kSuper + tid] = yro;
         }
         __syncthreads();
         // column partials of this super tile (buffer b is not written again before the next barrier)
@@ -640,8 +754,8 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, 
         if (rep == REP_SPLIT_F32) return launch_mb<double, REP_SPLIT_F32, PASS_REBASE>(g, a, st);
         if (rep == REP_SPLIT_BF16) return launch_mb<double, REP_SPLIT_BF16, PASS_REBASE>(g, a, st);
         return hipErrorInvalidValue;
-    case PASS_POWER:
-        if (fp32) return hipErrorInvalidValue;
+    case PASS_POWER:   // reads no multipliers: REP_F64 only sets the tile shape
+        if (fp32) return launch_mb<float, REP_F64, PASS_POWER>(g, a, st);
         return launch_mb<double, REP_F64, PASS_POWER>(g, a, st);
     case PASS_REPAIR:
         if (fp32) return hipErrorInvalidValue;
@@ -653,6 +767,14 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, 
         if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_TRIAL>(g, a, st);
         if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_TRIAL>(g, a, st);
         if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_TRIAL>(g, a, st);
+        return hipErrorInvalidValue;
+    case PASS_TRIAL_NS:
+        if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_TRIAL_NS>(g, a, st);
+        if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_TRIAL_NS>(g, a, st);
+        return hipErrorInvalidValue;
+    case PASS_ADV:
+        if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_ADV>(g, a, st);
+        if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_ADV>(g, a, st);
         return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
@@ -774,20 +896,28 @@ hipError_t launch_reduce(const double *part, int blocks, int stride, int nmax, i
     return hipGetLastError();
 }
 
-__global__ void normalize_kernel(double *y, double *xi, double *dmy, const double *sq, int Nr, int NP) {
+__global__ void normalize_kernel(double *y, double *xi, double *dmy, float *y32, float *xi32, float *dmy32,
+                                 const double *sq, int Nr, int NP) {
     const double f = 1.0 / sqrt(sq[0] + sq[1]);
     const size_t tot = (size_t)Nr * NP;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
-        xi[e] *= f;
-        if (e < (size_t)Nr) { y[e] *= f; dmy[e] *= f; }
+        const double v = xi[e] * f;
+        xi[e] = v;
+        if (xi32) xi32[e] = (float)v;
+        if (e < (size_t)Nr) {
+            const double a = y[e] * f, d = dmy[e] * f;
+            y[e] = a;
+            dmy[e] = d;
+            if (y32) { y32[e] = (float)a; dmy32[e] = (float)d; }
+        }
     }
 }
 
-hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dmy, const double *sq,
-                            hipStream_t st) {
+hipError_t launch_normalize(const Geometry &g, double *y, double *xi, double *dmy, float *y32, float *xi32,
+                            float *dmy32, const double *sq, hipStream_t st) {
     const int blocks = (int)(((size_t)g.Nr * g.NP + 255) / 256);
     hipLaunchKernelGGL(normalize_kernel, dim3(blocks < 4096 ? blocks : 4096), dim3(256), 0, st, y, xi,
-                       dmy, sq, g.Nr, g.NP);
+                       dmy, y32, xi32, dmy32, sq, g.Nr, g.NP);
     return hipGetLastError();
 }
 
@@ -899,8 +1029,8 @@ hipError_t launch_prepare(const Geometry &g, const double *x, const double *ybar
 }
 
 // One thread per padded row; thread-local sums only.
-__global__ void power_init_kernel(const double *xhat64, double *y, double *xi, double *dmy, int N, int n,
-                                  int Nr, int NP, double inv_norm) {
+__global__ void power_init_kernel(const double *xhat64, double *y, double *xi, double *dmy, float *y32,
+                                  float *xi32, float *dmy32, int N, int n, int Nr, int NP, double inv_norm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nr) return;
     double vy = 0.0, d = 0.0;
@@ -908,13 +1038,18 @@ __global__ void power_init_kernel(const double *xhat64, double *y, double *xi, d
         vy = (N > 1 ? -1.0 + 2.0 * (double)i / (double)(N - 1) : 0.0) * inv_norm;
         for (int m = 0; m < n; ++m) d += inv_norm * xhat64[(size_t)i * NP + m];
     }
-    for (int m = 0; m < NP; ++m) xi[(size_t)i * NP + m] = (i < N && m < n) ? inv_norm : 0.0;
+    for (int m = 0; m < NP; ++m) {
+        const double v = (i < N && m < n) ? inv_norm : 0.0;
+        xi[(size_t)i * NP + m] = v;
+        if (xi32) xi32[(size_t)i * NP + m] = (float)v;
+    }
     y[i] = vy;
     dmy[i] = d - vy;
+    if (y32) { y32[i] = (float)vy; dmy32[i] = (float)(d - vy); }
 }
 
 hipError_t launch_power_init(const Geometry &g, const double *xhat64, double *y, double *xi, double *dmy,
-                             hipStream_t st) {
+                             float *y32, float *xi32, float *dmy32, hipStream_t st) {
     // ||v||^2 = sum_l (-1 + 2l/(N-1))^2 + N n, summed on the host in a fixed order
     double s = 0.0;
     for (int l = 0; l < g.N; ++l) {
@@ -922,8 +1057,8 @@ hipError_t launch_power_init(const Geometry &g, const double *xhat64, double *y,
         s += v * v;
     }
     s += (double)g.N * (double)g.n;
-    hipLaunchKernelGGL(power_init_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, xhat64, y, xi, dmy, g.N,
-                       g.n, g.Nr, g.NP, 1.0 / sqrt(s));
+    hipLaunchKernelGGL(power_init_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, xhat64, y, xi, dmy, y32, xi32,
+                       dmy32, g.N, g.n, g.Nr, g.NP, 1.0 / sqrt(s));
     return hipGetLastError();
 }
 
@@ -1047,8 +1182,10 @@ hipError_t launch_lincomb(const Geometry &g, const double *ya, const double *xia
 
 // Accepted adaptive step: eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta) into
 // (ye, xie, dmye), then the next extrapolated point (1 + beta) eta(lam^{k+1}) - beta eta(lam^k) into
-// the pass arrays (y, xi, dmy and their FP32 copies).  (y, xi) hold eta(lam~^{k+1}) on entry.
-__global__ __launch_bounds__(256) void accept_kernel(double *y, double *xi, double *dmy, const double *uD,
+// the pass arrays (y, xi, dmy and their FP32 copies).  (yt, xit) hold eta(lam~^{k+1}); they may be
+// the same arrays as (y, xi).
+__global__ __launch_bounds__(256) void accept_kernel(const double *yt, const double *xit, double *y, double *xi,
+                                                    double *dmy, const double *uD,
                                                     const double *wD, const double *yk, const double *xik,
                                                     double *ye, double *xie, double *dmye, float *y32, float *xi32,
                                                     float *dmy32, const double *xhat64, double inv_delta, double beta,
@@ -1058,7 +1195,7 @@ __global__ __launch_bounds__(256) void accept_kernel(double *y, double *xi, doub
     double dn = 0.0, dp = 0.0;
     for (int m = t; m < NP; m += 16) {
         const size_t e = (size_t)i * NP + m;
-        const double xn = xi[e] + wD[e] * inv_delta;
+        const double xn = xit[e] + wD[e] * inv_delta;
         const double xp = (1.0 + beta) * xn - beta * xik[e];
         xie[e] = xn;
         xi[e] = xp;
@@ -1074,7 +1211,7 @@ __global__ __launch_bounds__(256) void accept_kernel(double *y, double *xi, doub
     }
     if (t == 0) {
         const bool valid = i < N;
-        const double yn = y[i] + uD[i];
+        const double yn = yt[i] + uD[i];
         const double yp = (1.0 + beta) * yn - beta * yk[i];
         ye[i] = yn;
         dmye[i] = valid ? dn - yn : 0.0;
@@ -1085,12 +1222,12 @@ __global__ __launch_bounds__(256) void accept_kernel(double *y, double *xi, doub
     }
 }
 
-hipError_t launch_accept(const Geometry &g, double *y, double *xi, double *dmy, const double *uD, const double *wD,
-                         const double *yk, const double *xik, double *ye, double *xie, double *dmye, float *y32,
-                         float *xi32, float *dmy32, const double *xhat64, double inv_delta, double beta,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, y, xi, dmy, uD, wD, yk, xik, ye, xie, dmye,
-                       y32, xi32, dmy32, xhat64, inv_delta, beta, g.N, g.n, g.NP);
+hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit, double *y, double *xi, double *dmy,
+                         const double *uD, const double *wD, const double *yk, const double *xik, double *ye,
+                         double *xie, double *dmye, float *y32, float *xi32, float *dmy32, const double *xhat64,
+                         double inv_delta, double beta, hipStream_t st) {
+    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, yt, xit, y, xi, dmy, uD, wD, yk, xik, ye,
+                       xie, dmye, y32, xi32, dmy32, xhat64, inv_delta, beta, g.N, g.n, g.NP);
     return hipGetLastError();
 }
 

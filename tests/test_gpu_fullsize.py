@@ -118,6 +118,36 @@ def test_adaptive_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
     assert np.all(got >= 0.0)
 
 
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+def test_reforming_trial_parity_N8000(cr, torch_dev, quad8000, precision):
+    """Split forms do not store the accepted candidate: the next trial pass re-forms it.  Solver A
+    stops after 4 and 5 iterations (each read-out stores the pending iterate); solver B runs 6
+    iterations back to back, so iterations 2-6 go through the re-forming pass.  The oracle steps
+    once from A's (lam^5, lam^4, s_5); B's lam^6 rows and s_6 must match."""
+    x, ybar = quad8000
+    delta = 1e-3
+    rows = np.random.default_rng(3).choice(8000, 48, replace=False)
+    opt = cr.Options(precision=precision, restart=False)
+    with cr.Solver(x, ybar, delta, opt) as s:
+        L, _, _ = s.lipschitz()
+        s.iterate(4)
+        lam4 = s.lam()
+        s.iterate(1)
+        lam5 = s.lam()
+        s5 = s.report()["step_final"]
+    with cr.Solver(x, ybar, delta, opt) as s:
+        s.set_L(L)
+        s.iterate(6)
+        rep = s.report()
+        got = np.vstack([s.lam_rows(int(r), 1) for r in rows])
+    assert rep["adv_passes"] >= 5
+    s6_ref, lam6 = _oracle_adaptive_step(x, ybar, delta, s5, lam5, lam4, 6)
+    assert rep["step_final"] == s6_ref
+    ref = lam6[rows]
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.abs(ref).max()
+    assert np.all(got >= 0.0)
+
+
 def test_report_parity_N8000(cr, torch_dev, quad8000):
     x, ybar = quad8000
     delta = 1e-3

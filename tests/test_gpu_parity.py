@@ -77,6 +77,19 @@ def test_lipschitz_matches_oracle(cr, torch_dev, wl, N, seed):
     assert abs(it - it0) <= 3
 
 
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+def test_lipschitz_mixed_coarse(cr, torch_dev, precision):
+    # adaptive step, default tolerance 1e-4: FP32 power passes; the estimate (from below) stays
+    # within the tolerance's reach of the oracle's converged value
+    x, ybar = W.make("quad_N8000_n40", seed=2, N=250)
+    L0, _, _ = oracle.lipschitz(x, 1e-3)
+    with cr.Solver(x, ybar, 1e-3, cr.Options(precision=precision)) as s:
+        L, _, it = s.lipschitz()
+    assert L == pytest.approx(L0, rel=2e-3)
+    assert L <= L0 * (1 + 1e-5)
+    assert it < 300
+
+
 @pytest.mark.parametrize("wl,N,seed,momentum", [("sqnorm_N200_n2", 200, 0, True), ("lse8_N2000_n10", 150, 1, True),
                                                  ("quad_N8000_n40", 130, 2, True), ("sqnorm_N200_n2", 77, 3, False)])
 def test_iterates_match_oracle(cr, torch_dev, wl, N, seed, momentum):
@@ -209,6 +222,30 @@ def test_adaptive_iterates_match_oracle(cr, torch_dev, wl, N, seed, momentum, re
         ry, rxi = oracle.primal_from_dual(x, ybar, delta, ref[50])
         assert _rel(y, ry) <= max(1e-10, 100.0 * spread)
         assert np.max(np.abs(xi - rxi)) <= max(1e-9, 100.0 * spread) * max(1.0, np.abs(rxi).max())
+
+
+@pytest.mark.parametrize("precision,restart", [("mixed_fp32", False), ("mixed_fp32", True), ("mixed_bf16", True)])
+def test_adaptive_iterates_mixed_match_oracle(cr, torch_dev, precision, restart):
+    """Split forms under the adaptive rule: the accepted candidate is re-formed by the next trial
+    pass instead of being stored.  The first 10 iterates agree with the FP64 oracle to the
+    mixed-precision bar (1e-4 of the multiplier scale)."""
+    x, ybar = W.make("lse8_N2000_n10", seed=1, N=150)
+    delta = 1e-3
+    L, _, _ = oracle.lipschitz(x, delta)
+    its = []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, iterates=its, adaptive=True,
+                restart=restart)
+    ref = dict(its)
+    with cr.Solver(x, ybar, delta, cr.Options(precision=precision, restart=restart)) as s:
+        s.set_L(L)
+        done = 0
+        for k in (1, 2, 3, 5, 10):
+            s.iterate(k - done)
+            done = k
+            lam = s.lam()
+            assert np.max(np.abs(lam - ref[k])) <= 1e-4 * np.abs(ref[k]).max(), k
+            assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
+        assert s.report()["adv_passes"] > 0
 
 
 # The adaptive rule's trajectory is sensitive to rounding: perturbing ybar by 1e-15 (relative) moves
