@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 WORKLOAD = "quad_N8000_n40"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1608_02227_amd", "csrc", "cr_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_step_traffic_quad_N8000_n40.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_traffic_quad_N8000_n40.json")
 
 
 def log(msg: str) -> None:
