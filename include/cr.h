@@ -81,7 +81,10 @@ typedef struct {
                                 <lam^{k+1} - lam~^{k+1}, lam^{k+1} - lam^k> < 0 (gradient restart
                                 of O'Donoghue and Candes); 0: the paper's schedule unchanged.
                                 Default 1 */
-    int32_t reserved[3];
+    int32_t stop_rule;       /* 0 (default): stop when report.kkt <= tol; 1: stop when the certified
+                                gap report.cert_gap <= tol, i.e. the multipliers are tol-optimal for
+                                the dual (the inner test of the continuation, Section 2.4.1) */
+    int32_t reserved[2];
 } cr_options;
 
 typedef struct {
@@ -166,6 +169,49 @@ int cr_fit_device(int64_t N, int64_t n, const double *x, const double *ybar, dou
                   double tol, const cr_options *opt, double *y, double *xi, double *lambda,
                   cr_report *rep);
 
+/*
+ * Continuation to the unregularized least-squares estimator (Section 2.4.1).
+ *   eps_t = eps0 / beta^t (beta > 1), outer iteration t = 1..T uses the Tikhonov weight
+ *   gamma_t = kappa_gamma eps_t and computes a delta_t-optimal dual solution, delta_t =
+ *   kappa_delta eps_t (certified gap <= delta_t), by P-APG started from the previous one
+ *   (theta^(0) = 0).  L_gamma = sigma_max(C)^2 / gamma_t reuses one power iteration.  By the
+ *   section's bound ||y^(t) - y*|| <= ||xi*|| sqrt(gamma_t) + sqrt(2 delta_t), y* the estimator
+ *   of eq. "original" (xi* its least-norm subgradients).
+ */
+typedef struct {
+    double eps0;             /* > 0 */
+    double beta;             /* > 1 */
+    double kappa_gamma;      /* > 0 */
+    double kappa_delta;      /* > 0 */
+    int32_t T;               /* outer iterations, >= 1 */
+    int32_t reserved;
+} cr_cont_params;
+
+typedef struct {
+    double gamma;            /* Tikhonov weight of this outer iteration */
+    double delta;            /* its dual tolerance (certified-gap target) */
+    int64_t iters;           /* inner P-APG iterations */
+    int32_t status;          /* CR_OK (certified gap <= delta), CR_ENOCONV or CR_ENUMERIC */
+    int32_t reserved;
+    double cert_gap;         /* certified gap at the end of the inner iterations */
+    double kkt;              /* KKT residual there (report.kkt) */
+    double xi_norm;          /* ||xi^(t)||_2 of the returned subgradients */
+    double seconds;          /* wall time of this outer iteration */
+} cr_cont_step;
+
+/*
+ * cr_fit_continuation - host arrays as in cr_fit.  opt->max_iters and opt->time_budget_s apply to
+ * each inner solve; opt->stop_rule is ignored (the certified gap is the inner test).  y, xi
+ * (required) receive (y^(T), xi^(T)); lambda (optional, N x N) theta^(T); steps (optional, T
+ * entries) one record per outer iteration; rep the report of the last inner solve with
+ * iters = the total over all outer iterations.  Returns CR_OK when every inner solve reached its
+ * tolerance, else the first failing inner status (the iterations go on with the next gamma_t
+ * after CR_ENOCONV).
+ */
+int cr_fit_continuation(int64_t N, int64_t n, const double *x, const double *ybar, const cr_cont_params *cp,
+                        const cr_options *opt, double *y, double *xi, double *lambda, cr_cont_step *steps,
+                        cr_report *rep);
+
 /* ---- Step-level entry points: a solver whose state stays on the device. ----------------- */
 typedef struct cr_solver cr_solver;
 
@@ -181,6 +227,12 @@ int cr_solver_destroy(cr_solver *s);
 int cr_solver_lipschitz(cr_solver *s, double *L, double *sigma2, int32_t *iters);
 /* Uses the given L (> 0) instead. */
 int cr_solver_set_L(cr_solver *s, double L);
+
+/* cr_solver_set_delta - change the Tikhonov weight of an existing solver (the continuation's
+ * gamma_t): the multipliers are kept as the warm start, L becomes sigma_max(C)^2 / delta when the
+ * power iteration has run (else it runs at the next solve), the FISTA sequence restarts (t = 1)
+ * and the adaptive step restarts from s = L.  delta > 0 and finite, else CR_EINVAL. */
+int cr_solver_set_delta(cr_solver *s, double delta);
 
 /* Advances the P-APG iteration `iters` times (accepted iterations under the adaptive rule) in the
  * solver's current precision. */

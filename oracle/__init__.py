@@ -11,9 +11,11 @@ Contents
 ``papg``   the method itself: the matrix-free constraint operator C and its adjoint, the closed-form
            Step 1 for the singleton partition (K = N), the Lipschitz constant by power iteration,
            the P-APG loop, the stopping report and the feasible-repair certificate.
-``exact``  an independent exact solver for tiny N that builds A1 and A2 explicitly from the
-           T_l blocks of Definition ``def:A1A2`` and solves the dual as a non-negative least
-           squares problem (Lawson-Hanson, via scipy).
+``exact``  independent exact solvers for tiny N that build A1 and A2 explicitly from the
+           T_l blocks of Definition ``def:A1A2``: the regularized dual as a non-negative least
+           squares problem (Lawson-Hanson, via scipy) and the unregularized estimator of
+           eq. ``original`` as a QP (SLSQP, via scipy).
+``continuation``  the outer loop of Section 2.4.1 (gamma_t, delta_t -> 0 with warm starts).
 
 All arithmetic is float64 with numpy's default round-to-nearest.  Each function cites the
 passage of the paper (Aybat & Wang, "A Parallelizable Dual Smoothing Method for Large Scale
@@ -31,4 +33,5 @@ from .papg import (  # noqa: F401
     kkt_report,
     repair_certificate,
 )
-from .exact import explicit_constraints, exact_solve  # noqa: F401
+from .exact import explicit_constraints, exact_solve, exact_ls  # noqa: F401
+from .continuation import continuation  # noqa: F401

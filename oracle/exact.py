@@ -59,3 +59,34 @@ def exact_solve(x: np.ndarray, ybar: np.ndarray, gamma: float, maxiter: int | No
     cons = A1 @ y + A2 @ xi.reshape(-1)
     return {"y": y, "xi": xi, "lam": lam, "p_star": p, "min_constraint": float(cons.min()),
             "theta": theta, "A1": A1, "A2": A2}
+
+
+def exact_ls(x: np.ndarray, ybar: np.ndarray) -> dict:
+    """The unregularized LS estimator of eq. ``original`` (gamma = 0) for tiny N.
+
+    y* is the projection of ybar onto the cone {y : A1 y + A2 xi >= 0 for some xi}: the convex QP
+    in (y, xi) is solved with scipy's SLSQP from the feasible start (mean(ybar), 0).  Its xi is one
+    subgradient choice; the least-norm subgradients xi* of eq. ``tikhonov`` (the limit of the
+    regularized solutions) solve min ||xi||^2 s.t. A2 xi >= -A1 y*, also by SLSQP.
+    """
+    from scipy.optimize import minimize
+    N, n = x.shape
+    A1, A2, _ = explicit_constraints(x)
+    A = np.hstack([A1, A2])
+
+    def f(z):
+        r = z[:N] - ybar
+        return 0.5 * float(r @ r), np.concatenate([r, np.zeros(N * n)])
+
+    z0 = np.concatenate([np.full(N, ybar.mean()), np.zeros(N * n)])
+    cons = [{"type": "ineq", "fun": lambda z: A @ z, "jac": lambda z: A}]
+    res = minimize(f, z0, jac=True, constraints=cons, method="SLSQP",
+                   options={"ftol": 1e-14, "maxiter": 5000})
+    y = res.x[:N]
+    b = -(A1 @ y)
+    res2 = minimize(lambda v: (0.5 * float(v @ v), v), np.zeros(N * n), jac=True,
+                    constraints=[{"type": "ineq", "fun": lambda v: A2 @ v - b, "jac": lambda v: A2}],
+                    method="SLSQP", options={"ftol": 1e-14, "maxiter": 5000})
+    return {"y": y, "xi": res2.x.reshape(N, n), "p_star": 0.5 * float((y - ybar) @ (y - ybar)),
+            "success": bool(res.success and res2.success), "message": (res.message, res2.message),
+            "min_constraint": float((A1 @ y + A2 @ res2.x).min())}

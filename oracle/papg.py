@@ -143,7 +143,7 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
          max_iters: int = 100000, check_every: int = 50, lam0: np.ndarray | None = None,
          momentum: bool = True, trace: list | None = None, iterates: list | None = None,
          adaptive: bool = False, upsilon: float = 2.0, steps: list | None = None,
-         restart: bool = False) -> dict:
+         restart: bool = False, stop: str = "kkt") -> dict:
     """Run P-APG (Fig. ``fig:papg``) from theta^0 = lam0 (default 0, as in Theorem ``bound``).
 
     Iteration k >= 1, with lam_tilde^1 = lam^0 and t_1 = 1:
@@ -173,7 +173,10 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
 
     Every ``check_every`` iterations the stopping report
     of ``kkt_report`` is evaluated at (lam^k, eta(lam^k)); the loop stops once its ``kkt`` is at
-    most ``tol``.  ``iterates``, when given, receives (k, lam^k) for every k.
+    most ``tol`` (``stop="kkt"``), or, with ``stop="gap"``, once the certified gap of
+    ``repair_certificate`` is at most ``tol``: G >= g* - g(lam^k), so lam^k is then tol-optimal in
+    the sense of Section 2.4.1 (a verifiable sufficient condition for the inner iterations of the
+    continuation).  ``iterates``, when given, receives (k, lam^k) for every k.
     """
     N = x.shape[0]
     if L is None:
@@ -218,14 +221,18 @@ def papg(x: np.ndarray, ybar: np.ndarray, gamma: float, tol: float, L: float | N
             iterates.append((k, lam.copy()))
         if k % check_every == 0 or k == max_iters:
             rep = kkt_report(x, ybar, gamma, lam)
+            if stop == "gap":
+                rep["cert_gap"] = repair_certificate(x, ybar, gamma, lam)["cert_gap"]
             if trace is not None:
                 trace.append((k, rep))
-            if rep["kkt"] <= tol:
+            if (rep["cert_gap"] if stop == "gap" else rep["kkt"]) <= tol:
                 status = "converged"
                 break
     y, xi = primal_from_dual(x, ybar, gamma, lam_prev)
-    if rep is None or rep.get("k") != k:
+    if rep is None or (k % check_every != 0 and k != max_iters):
         rep = kkt_report(x, ybar, gamma, lam_prev)
+    if stop == "gap" and "cert_gap" not in rep:
+        rep["cert_gap"] = repair_certificate(x, ybar, gamma, lam_prev)["cert_gap"]
     rep["k"] = k
     return {"y": y, "xi": xi, "lam": lam_prev, "L": L, "iters": k, "status": status,
             "report": rep, "step": s_k}
@@ -288,36 +295,78 @@ def kkt_report(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray,
     }
 
 
-def repair_certificate(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray) -> dict:
+def repair_certificate(x: np.ndarray, ybar: np.ndarray, gamma: float, lam: np.ndarray,
+                       rounds: int = 16) -> dict:
     """A feasible primal point built from eta(lam) and the certified gap it gives.
 
-    The fitted function f(z) = max_i (y_i + xi_i^T (z - x_i)) is convex; y'_j = f(x_j) and
-    xi'_j = xi_{i*(j)} with i*(j) the maximizing piece (j itself unless some other piece is
-    strictly larger; lowest index among ties) satisfy every pair constraint, so
-    p*_g <= r_g(y', xi') and, by weak duality, G = r_g(y', xi') - g(lam) >= p*_g - g(lam) >= 0.
-    Theorem ``thm:rate`` then bounds ||y(lam) - y*_g||^2 + g ||xi(lam) - xi*_g||^2 <= 2 G.
-    The largest |f(x_j) - y_j| equals the largest constraint violation of eta(lam).
+    Any feasible (y', xi') gives p*_g <= r_g(y', xi') and, by weak duality,
+    G = r_g(y', xi') - g(lam) >= p*_g - g(lam) >= 0; Theorem ``thm:rate`` then bounds
+    ||y(lam) - y*_g||^2 + g ||xi(lam) - xi*_g||^2 <= 2 G.  Two feasible points are built and the
+    smaller G is reported.
+
+    Max-affine repair: f(z) = max_i (y_i + xi_i^T (z - x_i)) is convex; y'_j = f(x_j) and xi'_j the
+    slope of a maximizing piece are feasible.  Near the optimum many pieces tie at x_j and rounding
+    decides which computes as the largest; switching to another piece's slope changes g||xi'||^2
+    by O(g ||xi||^2) for a rounding-level violation, so j keeps its own slope (y'_j still raised to
+    f(x_j)) unless some piece exceeds it by more than tau_j = 1e-10 (1 + |y_j| + ||xi_j||_1 X),
+    X = max_{l,m} |x_lm - mean_l x_lm|.
+
+    Own-slope (potential) repair: keep every xi_j and raise the heights, y' = y + c with the least
+    c >= 0 such that c_j >= c_i - s_ij for every pair (then s'_ij = s_ij + c_j - c_i >= 0).  The
+    least such c is a longest-path potential, reached by the relaxation
+    c_j <- max(c_j, max_{i != j} (c_i - s_ij)) from c = 0 (the first round gives the max-affine
+    heights); it exists when s has no negative cycle and is used when a round changes no c_j by
+    more than tau_j within ``rounds`` rounds.  Near the optimum c is of the order of the
+    violations, so G tracks the complementarity and the KKT residual.
+
+    Both points are feasible up to tau; G then bounds the suboptimality up to tau times the
+    multipliers' sum.
     """
     N = x.shape[0]
     y, xi = primal_from_dual(x, ybar, gamma, lam)
     s = pair_residual(x, y, xi)                  # s_jj = 0 stands for piece j itself
-    # f(x_j) = max_i (y_i + xi_i^T (x_j - x_i)) = y_j - min_i s_ij
+    g = dual_objective(x, ybar, gamma, lam)
+    xspan = float(np.abs(x - x.mean(axis=0)).max())
+    tau = 1e-10 * (1.0 + np.abs(y) + np.abs(xi).sum(axis=1) * xspan)
+    # max-affine repair: f(x_j) = max_i (y_i + xi_i^T (x_j - x_i)) = y_j - min_i s_ij
     colmin = s.min(axis=0)
     y_rep = y - colmin
     istar = np.arange(N)
-    viol = colmin < 0.0
+    viol = colmin < -tau
     istar[viol] = np.argmin(s[:, viol], axis=0)
     xi_rep = xi[istar]
-    g = dual_objective(x, ybar, gamma, lam)
     r_rep = primal_objective(ybar, gamma, y_rep, xi_rep)
-    G = r_rep - g
+    G_affine = r_rep - g
+    # own-slope repair
+    off = s.copy()
+    np.fill_diagonal(off, np.inf)
+    c = np.zeros(N)
+    converged = False
+    used = 0
+    for used in range(1, rounds + 1):
+        cand = np.maximum(c, (c[:, None] - off).max(axis=0))
+        changed = bool((cand > c + tau).any())
+        c = cand
+        if not changed:
+            converged = True
+            break
+    G_own = primal_objective(ybar, gamma, y + c, xi) - g if converged else math.inf
+    if G_own < G_affine:
+        y_best, xi_best, r_best, G, method = y + c, xi, G_own + g, G_own, "own-slope"
+    else:
+        y_best, xi_best, r_best, G, method = y_rep, xi_rep, r_rep, G_affine, "max-affine"
     return {
-        "y_rep": y_rep,
-        "xi_rep": xi_rep,
+        "y_rep": y_best,
+        "xi_rep": xi_best,
         "piece": istar,
-        "primal_rep": r_rep,
+        "primal_rep": r_best,
         "dual_obj": g,
         "cert_gap": G,
+        "cert_gap_affine": G_affine,
+        "cert_gap_own": G_own,
+        "own_rounds": used,
+        "own_converged": converged,
+        "method": method,
         "y_err_bound": math.sqrt(max(0.0, 2.0 * G)),
-        "max_fit_change": float(np.max(np.abs(y_rep - y))),
+        "max_fit_change": float(np.max(np.abs(y_best - y))),
     }

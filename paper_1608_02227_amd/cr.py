@@ -38,7 +38,8 @@ class CROptions(C.Structure):
         ("step_rule", C.c_int32),
         ("upsilon", C.c_double),
         ("restart", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("stop_rule", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -83,6 +84,20 @@ class CRReport(C.Structure):
 
 
 
+class CRContParams(C.Structure):
+    _fields_ = [("eps0", C.c_double), ("beta", C.c_double), ("kappa_gamma", C.c_double),
+                ("kappa_delta", C.c_double), ("T", C.c_int32), ("reserved", C.c_int32)]
+
+
+class CRContStep(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("delta", C.c_double), ("iters", C.c_int64), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("cert_gap", C.c_double), ("kkt", C.c_double), ("xi_norm", C.c_double),
+                ("seconds", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 class CRError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = code
@@ -119,6 +134,9 @@ def load() -> C.CDLL:
         "cr_solver_destroy": (C.c_int, [vp]),
         "cr_solver_lipschitz": (C.c_int, [vp, _P(d), _P(d), _P(i32)]),
         "cr_solver_set_L": (C.c_int, [vp, d]),
+        "cr_solver_set_delta": (C.c_int, [vp, d]),
+        "cr_fit_continuation": (C.c_int, [i64, i64, vp, vp, _P(CRContParams), _P(CROptions), vp, vp, vp,
+                                          _P(CRContStep), _P(CRReport)]),
         "cr_solver_iterate": (C.c_int, [vp, i64]),
         "cr_solver_solve": (C.c_int, [vp, d, _P(CRReport)]),
         "cr_solver_promote": (C.c_int, [vp]),
@@ -179,6 +197,7 @@ class Options:
     step_rule: str = "adaptive"     # "adaptive" (PAPG_A) or "constant" (PAPG_C, step 1/L)
     upsilon: float = 2.0
     restart: bool = True            # adaptive step: gradient momentum restart (not in the paper)
+    stop: str = "kkt"               # "kkt": report.kkt <= tol; "gap": certified gap <= tol
 
     def to_c(self) -> CROptions:
         o = CROptions()
@@ -198,6 +217,7 @@ class Options:
         o.step_rule = {"constant": 0, "adaptive": 1}[self.step_rule]
         o.upsilon = self.upsilon
         o.restart = 1 if self.restart else 0
+        o.stop_rule = {"kkt": 0, "gap": 1}[self.stop]
         return o
 
 
@@ -262,6 +282,32 @@ def fit(x, ybar, delta: float, tol: float, options: Options | None = None, retur
     return FitResult(y, xi, lam, rep.as_dict(), code)
 
 
+def fit_continuation(x, ybar, eps0: float, beta: float, kappa_gamma: float, kappa_delta: float, T: int,
+                     options: Options | None = None, return_lambda: bool = False,
+                     allow_noconv: bool = True) -> FitResult:
+    """Continuation to the unregularized estimator (cr_fit_continuation); host arrays.
+
+    extra["steps"] lists one record per outer iteration t (gamma, delta, iters, status, cert_gap,
+    kkt, xi_norm, seconds).
+    """
+    lib = load()
+    opt = options or Options()
+    x = _host(x)
+    N, n = x.shape
+    ybar = _host(ybar, (N,))
+    y = np.empty(N)
+    xi = np.empty((N, n))
+    lam = np.empty((N, N)) if return_lambda else None
+    cp = CRContParams(eps0, beta, kappa_gamma, kappa_delta, T, 0)
+    steps = (CRContStep * T)()
+    rep = CRReport()
+    co = opt.to_c()
+    code = lib.cr_fit_continuation(N, n, _ptr(x), _ptr(ybar), C.byref(cp), C.byref(co), _ptr(y), _ptr(xi),
+                                   _ptr(lam) if lam is not None else None, steps, C.byref(rep))
+    _check(code, "cr_fit_continuation", (CR_OK, CR_ENOCONV) if allow_noconv else (CR_OK,))
+    return FitResult(y, xi, lam, rep.as_dict(), code, {"steps": [st.as_dict() for st in steps]})
+
+
 class Solver:
     """Step-level access to one fit whose state stays on the device (cr_solver_*)."""
 
@@ -302,6 +348,11 @@ class Solver:
 
     def set_L(self, L: float):
         _check(load().cr_solver_set_L(self._h, L), "set_L")
+
+    def set_delta(self, delta: float):
+        """New Tikhonov weight; lam is kept as the warm start (one continuation step)."""
+        _check(load().cr_solver_set_delta(self._h, delta), "set_delta")
+        self.delta = delta
 
     def iterate(self, iters: int):
         _check(load().cr_solver_iterate(self._h, iters), "iterate")

@@ -150,6 +150,7 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->step_rule < 0 || opt->step_rule > 1) return CR_EINVAL;
         if (opt->step_rule == 1 && !(opt->upsilon > 1.0 && std::isfinite(opt->upsilon))) return CR_EINVAL;
         if (opt->restart < 0 || opt->restart > 1) return CR_EINVAL;
+        if (opt->stop_rule < 0 || opt->stop_rule > 1) return CR_EINVAL;
     }
     return CR_OK;
 }
@@ -244,6 +245,9 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     CR_ALLOC(s->part_min, (size_t)g.strips * g.ld * 8);
     CR_ALLOC(s->part_arg, (size_t)g.strips * g.ld * 4);
     CR_ALLOC(s->scal, 32 * 8);
+    CR_ALLOC(s->cpot[0], nr * 8);
+    CR_ALLOC(s->cpot[1], nr * 8);
+    CR_ALLOC(s->changed, (size_t)((g.Nr + 255) / 256) * 8);
     if (s->adaptive) {
         CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
         CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
@@ -280,11 +284,14 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     // on differences x_i - x_j, so (y, xi, lam) are unchanged while the float residual loses
     // less to cancellation.  The FP64 mode keeps the caller's coordinates.
     std::vector<double> mu((size_t)n, 0.0);
-    if (s->fp32pass) {
-        for (int64_t i = 0; i < N; ++i)
-            for (int64_t m = 0; m < n; ++m) mu[m] += hx[(size_t)i * n + m];
-        for (int64_t m = 0; m < n; ++m) mu[m] /= (double)N;
-    }
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t m = 0; m < n; ++m) mu[m] += hx[(size_t)i * n + m];
+    for (int64_t m = 0; m < n; ++m) mu[m] /= (double)N;
+    // spread of the centred locations: the rounding scale of the certificate's tie test
+    s->xspan = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t m = 0; m < n; ++m) s->xspan = std::max(s->xspan, std::fabs(hx[(size_t)i * n + m] - mu[m]));
+    if (!s->fp32pass) std::fill(mu.begin(), mu.end(), 0.0);   // the FP64 mode keeps the caller's frame
     int rc2 = CR_OK;
     auto H = [&](hipError_t e) { if (e != hipSuccess && rc2 == CR_OK) rc2 = fail_hip(e, "setup"); };
     H(hipMemcpyAsync(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, s->stream));
@@ -725,9 +732,31 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
         r.xhat = xhat64; r.xi = xic; r.yv = yc; r.dmy = dmyc;
         r.part_min = part_min; r.part_arg = part_arg;
         CR_HIP(launch_pass(g, PASS_REPAIR, false, REP_F64, r, stream));
-        CR_HIP(launch_repair_finish(g, part_min, part_arg, yc, xic, ybar64, yr, xir, rowred, stream));
+        CR_HIP(launch_repair_finish(g, part_min, part_arg, yc, xic, ybar64, yr, xir, rowred, xspan, stream));
         CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 6, stream));
-        nsc = 8;
+        // own-slope repair: relaxation rounds for the least height potentials c (the first round
+        // reuses the column minima above, offsets 0)
+        const int nb = (g.Nr + 255) / 256;
+        double *cin = cpot[0], *cout = cpot[1];
+        CR_HIP(hipMemsetAsync(cin, 0, (size_t)g.Nr * 8, stream));
+        own_converged = false;
+        own_rounds = 0;
+        for (int round = 1; round <= kOwnRounds; ++round) {
+            if (round > 1) {
+                PassArgs q = r;
+                q.row_off = cin;
+                CR_HIP(launch_pass(g, PASS_REPAIR, false, REP_F64, q, stream));
+            }
+            CR_HIP(launch_relax_finish(g, part_min, cin, cout, yc, xic, ybar64, xspan, rowred, changed, stream));
+            CR_HIP(launch_reduce(changed, nb, 1, 0, 1, scal + 8, stream));
+            CR_HIP(hipMemcpyAsync(h_scal + 8, scal + 8, sizeof(double), hipMemcpyDeviceToHost, stream));
+            CR_HIP(hipStreamSynchronize(stream));
+            own_rounds = round;
+            std::swap(cin, cout);
+            if (h_scal[8] == 0.0) { own_converged = true; break; }
+        }
+        if (own_converged) CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 1, scal + 8, stream));
+        nsc = own_converged ? 9 : 8;
     }
     CR_HIP(hipMemcpyAsync(h_scal, scal, nsc * sizeof(double), hipMemcpyDeviceToHost, stream));
     CR_HIP(hipStreamSynchronize(stream));
@@ -748,13 +777,19 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
     rep_out->comp_sum = h_scal[3];
     rep_out->dual_gap_paper = pairs > 0 ? std::fabs(h_scal[3]) / pairs : 0.0;
     rep_out->primal_obj = 0.5 * h_scal[4] + 0.5 * delta * h_scal[5];
+    xi_sq = h_scal[5];
     rep_out->dual_obj = rep_out->primal_obj - rep_out->comp_sum;
     // The returned (y, xi) are the FP64 closed form of lam^k, so stationarity holds to rounding.
     rep_out->stat_y = 0.0;
     rep_out->stat_xi = 0.0;
     rep_out->kkt = std::max(rep_out->nat_res_max, std::max(rep_out->stat_y, rep_out->stat_xi));
     if (certificate) {
+        // the smaller of the max-affine repair and (if its relaxation converged) the own-slope one
         rep_out->cert_primal = 0.5 * h_scal[6] + 0.5 * delta * h_scal[7];
+        if (own_converged) {
+            const double own = 0.5 * h_scal[8] + 0.5 * delta * h_scal[5];
+            if (own < rep_out->cert_primal) rep_out->cert_primal = own;
+        }
         rep_out->cert_gap = rep_out->cert_primal - rep_out->dual_obj;
         rep_out->y_err_bound = std::sqrt(std::max(0.0, 2.0 * rep_out->cert_gap));
     }
@@ -823,8 +858,9 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
     const int64_t kmax = opt.max_iters;
     const bool trace = getenv("CR_TRACE") != nullptr;
     // iteration 0 check: lam^0 may already be optimal (e.g. convex data)
+    const bool by_gap = opt.stop_rule == 1;
     for (;;) {
-        int rc = check(&rep, false);
+        int rc = check(&rep, by_gap);
         ++checks;
         if (trace)
             fprintf(stderr, "cr trace: k=%lld kkt=%.4e viol=%.4e infeas=%.4e dual=%.12e low=%d s/L=%.3e trials=%.0f "
@@ -832,7 +868,7 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
                     adaptive ? s_step / L : 1.0, trials, now_s() - t0);
         if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
         if (rc) return rc;
-        if (rep.kkt <= tol) { status = CR_OK; break; }
+        if ((by_gap ? rep.cert_gap : rep.kkt) <= tol) { status = CR_OK; break; }
         if (k >= kmax) break;
         if (opt.time_budget_s > 0.0 && now_s() - t0 > opt.time_budget_s) break;
         if (fp32pass) {
@@ -876,6 +912,20 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
 extern "C" int cr_solver_lipschitz(cr_solver *s, double *L, double *sigma2, int32_t *iters) {
     if (!s) return CR_EINVAL;
     return s->lipschitz(L, sigma2, iters);
+}
+
+extern "C" int cr_solver_set_delta(cr_solver *s, double delta) {
+    if (!s || !(delta > 0.0) || !std::isfinite(delta)) return CR_EINVAL;
+    CR_HIP(hipSetDevice(s->device));
+    int rc = s->materialize();
+    if (rc) return rc;
+    s->delta = delta;
+    s->L = s->sigma2 > 0.0 ? s->sigma2 / delta : 0.0;   // L_gamma = sigma_max(C)^2 / gamma
+    s->s_step = s->L;
+    s->t = 1.0;                                         // a fresh P-APG run from the current lam
+    s->beta_last = 0.0;
+    s->primed = false;
+    return CR_OK;
 }
 
 extern "C" int cr_solver_set_L(cr_solver *s, double L) {
@@ -1053,6 +1103,80 @@ static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, d
     if (rep) *rep = r;
     delete s;
     return status;
+}
+
+extern "C" int cr_fit_continuation(int64_t N, int64_t n, const double *x, const double *ybar,
+                                   const cr_cont_params *cp, const cr_options *opt_in, double *y, double *xi,
+                                   double *lambda, cr_cont_step *steps, cr_report *rep) {
+    const double t0 = now_s();
+    if (!cp || !x || !ybar || !y || !xi) return CR_EINVAL;
+    if (!(cp->eps0 > 0.0) || !(cp->beta > 1.0) || !(cp->kappa_gamma > 0.0) || !(cp->kappa_delta > 0.0) ||
+        !std::isfinite(cp->eps0 * cp->beta * cp->kappa_gamma * cp->kappa_delta) || cp->T < 1 || cp->T > 200)
+        return CR_EINVAL;
+    cr_options opt;
+    if (opt_in) opt = *opt_in; else cr_default_options(&opt);
+    opt.stop_rule = 1;   // delta_t-optimality, certified
+    auto gamma_at = [&](int t) { return cp->kappa_gamma * cp->eps0 / std::pow(cp->beta, t); };
+    auto delta_at = [&](int t) { return cp->kappa_delta * cp->eps0 / std::pow(cp->beta, t); };
+    int rc = validate(N, n, gamma_at(1), &opt);
+    if (rc) return rc;
+    if (N == 1) {
+        rc = fit_trivial(N, n, ybar, y, xi, lambda, rep, false, opt);
+        if (steps)
+            for (int t = 1; t <= cp->T; ++t) {
+                std::memset(&steps[t - 1], 0, sizeof(cr_cont_step));
+                steps[t - 1].gamma = gamma_at(t);
+                steps[t - 1].delta = delta_at(t);
+            }
+        return rc;
+    }
+    cr_solver *s = nullptr;
+    rc = cr_solver_create_impl(N, n, x, ybar, gamma_at(1), &opt, nullptr, false, &s);
+    if (rc) return rc;
+    // sigma_max(C)^2 once (an explicit opt.L is read as L at gamma_1)
+    if (opt.L > 0.0) { s->sigma2 = opt.L * gamma_at(1); }
+    else {
+        rc = s->lipschitz(nullptr, nullptr, nullptr);
+        if (rc) { delete s; return rc; }
+    }
+    int first_bad = CR_OK;
+    cr_report r{};
+    int64_t total = 0;
+    for (int t = 1; t <= cp->T; ++t) {
+        const double ts = now_s();
+        rc = cr_solver_set_delta(s, gamma_at(t));
+        if (rc) { delete s; return rc; }
+        const int64_t k0 = s->k;
+        const int status = s->solve(delta_at(t), &r);
+        if (status != CR_OK && status != CR_ENOCONV && status != CR_ENUMERIC) { delete s; return status; }
+        if (status != CR_OK && first_bad == CR_OK) first_bad = status;
+        total = s->k;
+        if (steps) {
+            cr_cont_step &st = steps[t - 1];
+            std::memset(&st, 0, sizeof(st));
+            st.gamma = gamma_at(t);
+            st.delta = delta_at(t);
+            st.iters = s->k - k0;
+            st.status = status;
+            st.cert_gap = r.cert_gap;
+            st.kkt = r.kkt;
+            st.xi_norm = std::sqrt(std::max(0.0, s->xi_sq));
+            st.seconds = now_s() - ts;
+        }
+        if (status == CR_ENUMERIC) break;
+    }
+    // (y, xi) of the last check, lambda if asked
+    rc = primal_out(s, s->yc, s->xic, y, xi, false);
+    if (rc) { delete s; return rc; }
+    if (lambda) {
+        rc = cr_solver_get_lambda(s, lambda);
+        if (rc) { delete s; return rc; }
+    }
+    r.iters = total;
+    r.seconds = now_s() - t0;
+    if (rep) *rep = r;
+    delete s;
+    return first_bad;
 }
 
 extern "C" int cr_fit(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,

@@ -54,6 +54,14 @@ struct cr_solver {
     double s_step = 0.0;         // s_k of the adaptive rule (starts at L)
     double trials = 0.0;
     double restarts = 0.0;
+    double xspan = 0.0;          // max |x - mean(x)| (certificate tie test)
+    double xi_sq = 0.0;          // ||xi(lam^k)||^2 at the last stopping test
+    // own-slope repair of the certificate: height potentials (ping-pong), per-block change counts
+    static constexpr int kOwnRounds = 16;
+    double *cpot[2] = {nullptr, nullptr};
+    double *changed = nullptr;
+    bool own_converged = false;
+    int own_rounds = 0;
     double *part_red = nullptr, *part_min = nullptr;
     int *part_arg = nullptr;
     double *scal = nullptr;

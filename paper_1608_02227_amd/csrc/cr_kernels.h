@@ -111,6 +111,9 @@ struct PassArgs {
     const void *yv_o;
     const void *dmy_o;
     double inv_Lo;      // 1 / s_k of the accepted candidate being re-formed
+    // PASS_REPAIR only (optional): per-row offsets c_i; the pass then takes column minima of
+    // s_ij - c_i (the relaxation rounds of the own-slope repair)
+    const double *row_off;
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,
@@ -204,11 +207,20 @@ hipError_t launch_pad_primal(const Geometry &g, const double *y_in, const double
                              const double *xhat64, double *y, double *xi, double *dmy,
                              hipStream_t st);
 
-// Repair: for column j, colmin over strips -> y'_j = y_j - min(0, colmin), piece_j; writes
-// y'(Nr), xi'(Nr x NP) and rowred' (Nr x 2) for the objective.
+// Repair: for column j, colmin over strips -> y'_j = y_j - min(0, colmin); xi'_j is the slope of
+// the arg-min piece if colmin < -tau_j, else xi_j, with tau_j = 1e-10 (1 + |y_j| + ||xi_j||_1 xspan)
+// (xspan = max |x - mean(x)|); writes y'(Nr), xi'(Nr x NP) and rowred' (Nr x 2) for the objective.
 hipError_t launch_repair_finish(const Geometry &g, const double *part_min, const int *part_arg,
                                 const double *y, const double *xi, const double *ybar,
-                                double *y_rep, double *xi_rep, double *rowred, hipStream_t st);
+                                double *y_rep, double *xi_rep, double *rowred, double xspan, hipStream_t st);
+
+// One relaxation round of the own-slope repair from the column minima m_j = min_i (s_ij - c_i) of a
+// PASS_REPAIR with offsets c_in: c_out_j = max(c_in_j, -m_j) (padding 0); rowred_j =
+// (y_j + c_out_j - ybar_j)^2; changed[b] = number of columns of block b (256 columns) whose c grew
+// by more than tau_j (as in launch_repair_finish).  Grid: ceil(Nr / 256) blocks.
+hipError_t launch_relax_finish(const Geometry &g, const double *part_min, const double *c_in, double *c_out,
+                               const double *y, const double *xi, const double *ybar, double xspan,
+                               double *rowred, double *changed, hipStream_t st);
 
 // Copies the FP64 y (Nr) and xi (Nr x NP) to dense N and N x n arrays.
 hipError_t launch_unpad_primal(const Geometry &g, const double *y, const double *xi,

@@ -208,6 +208,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     for (int s = 0; s < 4 * MB; ++s)
         bxi[s] = kResidual ? xi[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmy_i = kResidual ? dmy[i] : (T)0;
+    const T roff_i = (MODE == PASS_REPAIR && a.row_off) ? (T)a.row_off[i] : (T)0;
     // PASS_ADV: the previous trial's row operands (re-forming its accepted candidate)
     const T *xio = static_cast<const T *>(a.xi_o);
     const T *yvo = static_cast<const T *>(a.yv_o);
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     }
                     out[c] = (T)0;
                 } else if constexpr (MODE == PASS_REPAIR) {
-                    out[c] = ok ? s : (T)INFINITY;
+                    out[c] = ok ? s - roff_i : (T)INFINITY;
                 } else {  // PASS_RESID (REP_F64)
                     cur.q[c] = ok ? (double)s : 0.0;
                     out[c] = (T)0;
@@ -1088,7 +1089,8 @@ hipError_t launch_pad_primal(const Geometry &g, const double *y_in, const double
 // row index is kept on ties); the piece is j itself unless the minimum is negative.
 __global__ void repair_finish_kernel(const double *part_min, const int *part_arg, const double *y,
                                      const double *xi, const double *ybar, double *y_rep, double *xi_rep,
-                                     double *rowred, int N, int Nr, int ld, int strips, int NP) {
+                                     double *rowred, double xspan, int N, int Nr, int ld, int strips,
+                                     int NP) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Nr) return;
     if (j >= N) {
@@ -1104,8 +1106,13 @@ __global__ void repair_finish_kernel(const double *part_min, const int *part_arg
         const double v = part_min[(size_t)s * ld + j];
         if (v < best) { best = v; arg = part_arg[(size_t)s * ld + j]; }
     }
+    // j keeps its own slope unless another piece exceeds it by more than the rounding scale
+    // (ties at the optimum are decided by rounding; switching slopes there would inflate the gap)
+    double xi1 = 0.0;
+    for (int m = 0; m < NP; ++m) xi1 += fabs(xi[(size_t)j * NP + m]);
+    const double tau = 1e-10 * (1.0 + fabs(y[j]) + xi1 * xspan);
     const double shift = best < 0.0 ? best : 0.0;
-    const int piece = best < 0.0 ? arg : j;
+    const int piece = best < -tau ? arg : j;
     const double yr = y[j] - shift;
     y_rep[j] = yr;
     double xsq = 0.0;
@@ -1119,11 +1126,54 @@ __global__ void repair_finish_kernel(const double *part_min, const int *part_arg
     rowred[2 * (size_t)j + 1] = xsq;
 }
 
+__global__ __launch_bounds__(256) void relax_finish_kernel(const double *part_min, const double *c_in,
+                                                          double *c_out, const double *y, const double *xi,
+                                                          const double *ybar, double xspan, double *rowred,
+                                                          double *changed, int N, int Nr, int ld, int strips,
+                                                          int NP) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    int grew = 0;
+    if (j < N) {
+        double m = INFINITY;
+        for (int s = 0; s < strips; ++s) m = fmin(m, part_min[(size_t)s * ld + j]);
+        const double c0 = c_in[j];
+        const double c1 = fmax(c0, -m);
+        double xi1 = 0.0;
+        for (int q = 0; q < NP; ++q) xi1 += fabs(xi[(size_t)j * NP + q]);
+        const double tau = 1e-10 * (1.0 + fabs(y[j]) + xi1 * xspan);
+        grew = c1 > c0 + tau ? 1 : 0;
+        c_out[j] = c1;
+        const double dy = y[j] + c1 - ybar[j];
+        rowred[2 * (size_t)j] = dy * dy;
+        rowred[2 * (size_t)j + 1] = 0.0;
+    } else if (j < Nr) {
+        c_out[j] = 0.0;
+        rowred[2 * (size_t)j] = 0.0;
+        rowred[2 * (size_t)j + 1] = 0.0;
+    }
+    __shared__ int sh[256];
+    sh[threadIdx.x] = grew;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) changed[blockIdx.x] = (double)sh[0];
+}
+
+hipError_t launch_relax_finish(const Geometry &g, const double *part_min, const double *c_in, double *c_out,
+                               const double *y, const double *xi, const double *ybar, double xspan,
+                               double *rowred, double *changed, hipStream_t st) {
+    hipLaunchKernelGGL(relax_finish_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, part_min, c_in, c_out, y, xi,
+                       ybar, xspan, rowred, changed, g.N, g.Nr, g.ld, g.strips, g.NP);
+    return hipGetLastError();
+}
+
 hipError_t launch_repair_finish(const Geometry &g, const double *part_min, const int *part_arg, const double *y,
                                 const double *xi, const double *ybar, double *y_rep, double *xi_rep,
-                                double *rowred, hipStream_t st) {
+                                double *rowred, double xspan, hipStream_t st) {
     hipLaunchKernelGGL(repair_finish_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, part_min, part_arg, y, xi,
-                       ybar, y_rep, xi_rep, rowred, g.N, g.Nr, g.ld, g.strips, g.NP);
+                       ybar, y_rep, xi_rep, rowred, xspan, g.N, g.Nr, g.ld, g.strips, g.NP);
     return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ def test_fit_rejects_bad_options_on_host(cr):
     xi = np.zeros((4, 2))
     for field, value in [("check_every", 0), ("precision", 7), ("L", -1.0), ("power_max_iters", 0),
                          ("step_rule", 2), ("upsilon", 1.0), ("upsilon", float("inf")), ("restart", 2),
-                         ("power_rtol", -1.0)]:
+                         ("power_rtol", -1.0), ("stop_rule", 2)]:
         opt = cr.Options().to_c()
         setattr(opt, field, value)
         rc = lib.cr_fit(4, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)
@@ -75,20 +75,35 @@ def test_binding_struct_layout_matches_header(cr, tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
-    fields_o = [f for f, _ in cr.CROptions._fields_]
-    fields_r = [f for f, _ in cr.CRReport._fields_]
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cr.h"', "int main(void){",
-             'printf("%zu %zu\\n", sizeof(cr_options), sizeof(cr_report));']
-    lines += [f'printf("%zu\\n", offsetof(cr_options, {f}));' for f in fields_o]
-    lines += [f'printf("%zu\\n", offsetof(cr_report, {f}));' for f in fields_r]
+    structs = [("cr_options", cr.CROptions), ("cr_report", cr.CRReport), ("cr_cont_params", cr.CRContParams),
+               ("cr_cont_step", cr.CRContStep)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cr.h"', "int main(void){"]
+    lines += [f'printf("%zu\\n", sizeof({name}));' for name, _ in structs]
+    for name, py in structs:
+        lines += [f'printf("%zu\\n", offsetof({name}, {f}));' for f, _ in py._fields_]
     lines += ["return 0;}"]
     src = tmp_path / "probe.c"
     src.write_text("\n".join(lines))
     exe = tmp_path / "probe"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    assert int(out[0]) == C.sizeof(cr.CROptions)
-    assert int(out[1]) == C.sizeof(cr.CRReport)
-    offs = [int(v) for v in out[2:]]
-    py = [getattr(cr.CROptions, f).offset for f in fields_o] + [getattr(cr.CRReport, f).offset for f in fields_r]
+    assert [int(v) for v in out[:len(structs)]] == [C.sizeof(py) for _, py in structs]
+    offs = [int(v) for v in out[len(structs):]]
+    py = [getattr(p, f).offset for _, p in structs for f, _ in p._fields_]
     assert offs == py
+
+
+@pytest.mark.parametrize("field,value", [("eps0", 0.0), ("beta", 1.0), ("kappa_gamma", -1.0), ("kappa_delta", 0.0),
+                                         ("T", 0)])
+def test_continuation_rejects_bad_parameters_on_host(cr, field, value):
+    lib = cr.load()
+    x = np.zeros((4, 2))
+    yb = np.zeros(4)
+    y = np.zeros(4)
+    xi = np.zeros((4, 2))
+    cp = cr.CRContParams(1.0, 2.0, 1.0, 1.0, 3, 0)
+    setattr(cp, field, value)
+    opt = cr.Options().to_c()
+    rc = lib.cr_fit_continuation(4, 2, cr._ptr(x), cr._ptr(yb), C.byref(cp), C.byref(opt), cr._ptr(y), cr._ptr(xi),
+                                 None, None, None)
+    assert rc == cr.CR_EINVAL

@@ -1,0 +1,68 @@
+"""GPU continuation (Section 2.4.1) against the oracle and the exact unregularized estimator.
+
+Each outer iteration stops at a certified gap G <= delta_t, so by Theorem ``thm:rate`` both the
+GPU's and the oracle's y^(t) lie within sqrt(2 G) of the regularized optimum y*_{gamma_t}; the bar
+between them is the sum of the two radii.  The last iterate is compared with the exact estimator
+y* of eq. ``original`` under the section's bound ||xi*|| sqrt(gamma_T) + sqrt(2 delta_T).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_02227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return torch
+
+
+@pytest.mark.parametrize("precision,seed,kind", [("fp64", 5, "sq"), ("fp64", 7, "lse"), ("mixed_fp32", 6, "sq")])
+def test_continuation_matches_oracle_and_bound(cr, torch_dev, precision, seed, kind):
+    if kind == "sq":
+        x, ybar = W.sq_norm(12, 2, 0.1, seed)
+    else:
+        x, ybar = W.log_sum_exp_affine(12, 3, 4, 0.2, seed)
+    T = 10
+    ref = oracle.continuation(x, ybar, eps0=1.0, beta=2.0, kappa_gamma=1.0, kappa_delta=1.0, T=T)
+    r = cr.fit_continuation(x, ybar, 1.0, 2.0, 1.0, 1.0, T, cr.Options(precision=precision, check_every=10),
+                            allow_noconv=False)
+    steps = r.extra["steps"]
+    assert len(steps) == T
+    for t, (st, o) in enumerate(zip(steps, ref), start=1):
+        assert st["gamma"] == pytest.approx(2.0 ** -t, rel=1e-15) and st["delta"] == st["gamma"]
+        assert st["status"] == cr.CR_OK and 0.0 <= st["cert_gap"] <= st["delta"]
+    # the final iterate against the oracle's (both within sqrt(2 G) of y*_gamma_T)
+    gap_o = ref[-1]["cert_gap"]
+    gap_g = steps[-1]["cert_gap"]
+    assert np.linalg.norm(r.y - ref[-1]["y"]) <= math.sqrt(2 * gap_o) + math.sqrt(2 * gap_g) + 1e-9
+    # and against the exact unregularized estimator (Section 2.4.1)
+    ex = oracle.exact_ls(x, ybar)
+    bound = np.linalg.norm(ex["xi"]) * math.sqrt(steps[-1]["gamma"]) + math.sqrt(2 * steps[-1]["delta"])
+    assert np.linalg.norm(r.y - ex["y"]) <= bound
+    assert r.report["iters"] == sum(st["iters"] for st in steps)
+
+
+def test_set_delta_warm_start_matches_oracle(cr, torch_dev):
+    # one continuation step by hand: solve at gamma_1, change the weight, solve again from there
+    x, ybar = W.sq_norm(40, 2, 0.1, 9)
+    g1, g2, tol = 1e-2, 2.5e-3, 1e-9
+    with cr.Solver(x, ybar, g1, cr.Options(stop="gap", check_every=10)) as s:
+        s.lipschitz()
+        code, rep1 = s.solve(tol)
+        assert code == cr.CR_OK and rep1["cert_gap"] <= tol
+        s.set_delta(g2)
+        code, rep2 = s.solve(tol)
+        assert code == cr.CR_OK and rep2["cert_gap"] <= tol
+        y, _ = s.primal()
+    ex = oracle.exact_solve(x, ybar, g2)
+    # certified: ||y - y*_gamma|| <= sqrt(2 G)
+    assert np.linalg.norm(y - ex["y"]) <= math.sqrt(2 * rep2["cert_gap"]) + 1e-9
+    assert rep2["L"] == pytest.approx(rep1["L"] * g1 / g2, rel=1e-12)

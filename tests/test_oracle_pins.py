@@ -339,7 +339,33 @@ def test_certificate_brackets_true_error(iters):
     err = np.linalg.norm(r["y"] - ex["y"])
     assert err <= c["y_err_bound"] * (1 + 1e-9) + 1e-12
     rep = oracle.kkt_report(x, ybar, gamma, r["lam"])
-    assert c["max_fit_change"] == pytest.approx(rep["max_viol"] * rep["scale"], rel=1e-9, abs=1e-14)
+    if c["method"] == "max-affine":
+        assert c["max_fit_change"] == pytest.approx(rep["max_viol"] * rep["scale"], rel=1e-9, abs=1e-14)
+    else:   # the potentials are at least the first relaxation round (the max-affine heights)
+        assert c["max_fit_change"] >= rep["max_viol"] * rep["scale"] * (1 - 1e-9) - 1e-14
+
+
+@pytest.mark.parametrize("seed,iters", [(8, 300), (9, 1000), (10, 3000)])
+def test_own_slope_certificate_is_feasible_and_tight(seed, iters):
+    x, ybar = W.sq_norm(14, 2, 0.1, seed)
+    gamma = 1e-2
+    ex = exact_solve(x, ybar, gamma)
+    r = oracle.papg(x, ybar, gamma, 0.0, max_iters=iters, check_every=10 ** 9, adaptive=True, restart=True)
+    c = oracle.repair_certificate(x, ybar, gamma, r["lam"])
+    assert c["own_converged"]
+    A1, A2 = ex["A1"], ex["A2"]
+    y, xi = oracle.primal_from_dual(x, ybar, gamma, r["lam"])
+    # own-slope point: the same subgradients, heights raised by the potentials
+    yo = y + (c["y_rep"] - y) if c["method"] == "own-slope" else None
+    if yo is not None:
+        np.testing.assert_array_equal(c["xi_rep"], xi)
+        assert np.all(c["y_rep"] >= y - 1e-15)
+        cons = A1 @ c["y_rep"] + A2 @ c["xi_rep"].reshape(-1)
+        assert cons.min() >= -1e-9
+    # both certificates bracket the true suboptimality; the reported one is the smaller
+    true_sub = ex["p_star"] - oracle.dual_objective(x, ybar, gamma, r["lam"])
+    assert c["cert_gap_affine"] >= true_sub - 1e-12 and c["cert_gap_own"] >= true_sub - 1e-12
+    assert c["cert_gap"] == min(c["cert_gap_affine"], c["cert_gap_own"])
 
 
 # --- invariances (PIN-6) ---------------------------------------------------------------------
