@@ -168,6 +168,32 @@ def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restar
             "N_range": [int(min(r.x.shape[0] for r in reqs)), int(max(r.x.shape[0] for r in reqs))]}
 
 
+def run_continuation(cr, W, T: int, precision: str) -> dict:
+    """Continuation to the unregularized estimator (Section 2.4.1) on the N=8000, n=40 workload.
+
+    eps_t = 1 / 2^t, gamma_t = 1e-2 eps_t, delta_t = eps_t; each outer step stops at a certified
+    gap <= delta_t.  The accuracy bound per step is the section's ||xi|| sqrt(gamma_t) +
+    sqrt(2 delta_t) with ||xi^(t)|| standing in for ||xi*||, divided by sqrt(N) (the paper's
+    Accuracy scale).
+    """
+    wl = W.WORKLOADS[WORKLOAD]
+    x, yb = W.make(WORKLOAD, seed=0)
+    t0 = time.perf_counter()
+    r = cr.fit_continuation(x, yb, 1.0, 2.0, 1e-2, 1.0, T, cr.Options(precision=precision))
+    dt = time.perf_counter() - t0
+    steps = []
+    for st in r.extra["steps"]:
+        acc = (st["xi_norm"] * math.sqrt(st["gamma"]) + math.sqrt(2.0 * st["delta"])) / math.sqrt(wl.N)
+        steps.append({"gamma": st["gamma"], "delta": st["delta"], "iters": st["iters"], "status": st["status"],
+                      "cert_gap": st["cert_gap"], "kkt": st["kkt"], "seconds": round(st["seconds"], 4),
+                      "accuracy_bound": acc})
+    log(f"continuation: {T} outer steps, {r.report['iters']} iterations in {dt:.2f} s, "
+        f"accuracy bound {steps[-1]['accuracy_bound']:.3e}")
+    return {"workload": WORKLOAD, "precision": precision, "eps0": 1.0, "beta": 2.0, "kappa_gamma": 1e-2,
+            "kappa_delta": 1.0, "T": T, "status": r.status, "total_iters": r.report["iters"],
+            "seconds_host_arrays": round(dt, 3), "steps": steps}
+
+
 def run_large(cr, W, iters: int, precision: str, rule: str, restart: bool) -> dict:
     """K iterations of the N=40000, n=20 fit (the largest workload; 1.6e9 pairs)."""
     name = "maxaff16_N40000_n20"
@@ -216,6 +242,8 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=0, metavar="K",
                     help="also replay K requests of the serving stream (Poisson, 50/s) and report latency")
     ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
+    ap.add_argument("--continuation", type=int, default=6, metavar="T",
+                    help="also run T outer steps of the continuation to the unregularized estimator (0: skip)")
     ap.add_argument("--large", type=int, default=300, metavar="K",
                     help="also run K iterations of the N=40000, n=20 fit and report its pass rate (0: skip)")
     args = ap.parse_args()
@@ -368,6 +396,8 @@ def main() -> int:
     }
     if args.serving > 0:
         out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision, rule, restart)
+    if args.continuation > 0:
+        out["continuation"] = run_continuation(cr, W, args.continuation, args.precision)
     if args.large > 0:
         out["large_fit"] = run_large(cr, W, args.large, args.precision, rule, restart)
     if not args.no_cpu:
