@@ -252,6 +252,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
         CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
         CR_ALLOC(s->block_part, (size_t)(g.Nr / 16) * 4 * 8);
+        CR_ALLOC(s->ticket, 256);
         for (int q = 0; q < 2; ++q) {
             CR_ALLOC(s->uD[q], nr * 8);
             CR_ALLOC(s->wD[q], rows_np * 8);
@@ -326,6 +327,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     H(hipMemsetAsync(s->part_acc, 0, (size_t)g.chunks * rows_np * 8, s->stream));
     H(hipMemsetAsync(s->part_col, 0, (size_t)g.strips * g.ld * 8, s->stream));
     if (s->adaptive) {
+        H(hipMemsetAsync(s->ticket, 0, 256, s->stream));
         H(hipMemsetAsync(s->part_acc2, 0, (size_t)g.chunks * rows_np * 8, s->stream));
         H(hipMemsetAsync(s->part_col2, 0, (size_t)g.strips * g.ld * 8, s->stream));
     }
@@ -520,8 +522,9 @@ int cr_solver::step_adaptive() {
         } else {
             a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
         }
-        // the timed launches are the dominant kind: re-forming trials (split) or storing trials
-        const bool timed = !ev_pending && (adv || !defer);
+        // the timed launches are the dominant kind: re-forming trials (split) or storing trials;
+        // one in four is sampled
+        const bool timed = !ev_pending && (adv || !defer) && (timing_tick++ % 4 == 0);
         if (timed) CR_HIP(hipEventRecord(ev_a, stream));
         CR_HIP(launch_pass(g, adv ? PASS_ADV : (defer ? PASS_TRIAL_NS : PASS_TRIAL), fp32pass, rep, a, stream));
         if (timed) {
@@ -542,11 +545,13 @@ int cr_solver::step_adaptive() {
         f.uD[0] = uD[0]; f.uD[1] = uD[1];
         f.wD[0] = wD[0]; f.wD[1] = wD[1];
         f.block_part = block_part;
+        // h_scal (pinned host memory) receives ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b,
+        // ||D_a||^2, ||D_b||^2, <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>
+        f.part_red = part_red;
+        f.pass_blocks = g.grid();
+        f.ticket = ticket;
+        f.out = h_scal;
         CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
-        // scal: ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b, ||D_a||^2, ||D_b||^2,
-        //       <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>
-        CR_HIP(launch_reduce2(block_part, g.Nr / 16, 4, 4, part_red, g.grid(), kRed, 4, scal, stream));
-        CR_HIP(hipMemcpyAsync(h_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
         CR_HIP(hipStreamSynchronize(stream));
         collect_timing();
         trials += 2.0;

@@ -1334,6 +1334,37 @@ __global__ __launch_bounds__(256) void trial_finalize_kernel(TrialFinalizeArgs a
         for (int rr = 0; rr < 16; ++rr) s += sh[rr][threadIdx.x];
         a.block_part[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
     }
+    // the last workgroup to finish reduces everything (its reads see the others' partials after
+    // the release / acquire fences around the ticket)
+    __shared__ int am_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        am_last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!am_last) return;
+    __threadfence();
+    __shared__ double red[8][256];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double v = 0.0;
+        if (q < 4) {
+            for (int bb = threadIdx.x; bb < (int)gridDim.x; bb += 256) v += a.block_part[(size_t)bb * 4 + q];
+        } else {
+            for (int bb = threadIdx.x; bb < a.pass_blocks; bb += 256) v += a.part_red[(size_t)bb * kRed + q - 4];
+        }
+        red[q][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) a.out[threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x == 0) *a.ticket = 0u;
 }
 
 hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st) {
@@ -1349,36 +1380,6 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
                         default: return hipErrorInvalidValue; }
     }
 #undef CR_TFIN
-    return hipGetLastError();
-}
-
-// Two independent sets of column sums in one single-workgroup launch, fixed order:
-// out[q] = sum_b a[b * sa + q] for q < na, then out[na + q] = sum_b b[b * sb + q] for q < nb.
-__global__ __launch_bounds__(256) void reduce2_kernel(const double *pa, int ba, int sa, int na, const double *pb,
-                                                     int bb, int sb, int nb, double *out) {
-    __shared__ double sh[8][256];
-    const int nt = na + nb;
-    for (int q = 0; q < nt; ++q) {
-        const bool first = q < na;
-        const double *p = first ? pa : pb;
-        const int blocks = first ? ba : bb, stride = first ? sa : sb, col = first ? q : q - na;
-        double v = 0.0;
-        for (int b = threadIdx.x; b < blocks; b += 256) v += p[(size_t)b * stride + col];
-        sh[q][threadIdx.x] = v;
-    }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-            for (int q = 0; q < nt; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x < nt) out[threadIdx.x] = sh[threadIdx.x][0];
-}
-
-hipError_t launch_reduce2(const double *pa, int ba, int sa, int na, const double *pb, int bb, int sb, int nb,
-                          double *out, hipStream_t st) {
-    if (na + nb > 8 || na < 0 || nb < 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(256), 0, st, pa, ba, sa, na, pb, bb, sb, nb, out);
     return hipGetLastError();
 }
 
