@@ -252,7 +252,6 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
         CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
         CR_ALLOC(s->block_part, (size_t)(g.Nr / 16) * 4 * 8);
-        CR_ALLOC(s->ticket, 256);
         for (int q = 0; q < 2; ++q) {
             CR_ALLOC(s->uD[q], nr * 8);
             CR_ALLOC(s->wD[q], rows_np * 8);
@@ -327,7 +326,6 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     H(hipMemsetAsync(s->part_acc, 0, (size_t)g.chunks * rows_np * 8, s->stream));
     H(hipMemsetAsync(s->part_col, 0, (size_t)g.strips * g.ld * 8, s->stream));
     if (s->adaptive) {
-        H(hipMemsetAsync(s->ticket, 0, 256, s->stream));
         H(hipMemsetAsync(s->part_acc2, 0, (size_t)g.chunks * rows_np * 8, s->stream));
         H(hipMemsetAsync(s->part_col2, 0, (size_t)g.strips * g.ld * 8, s->stream));
     }
@@ -547,11 +545,8 @@ int cr_solver::step_adaptive() {
         f.block_part = block_part;
         // h_scal (pinned host memory) receives ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b,
         // ||D_a||^2, ||D_b||^2, <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>
-        f.part_red = part_red;
-        f.pass_blocks = g.grid();
-        f.ticket = ticket;
-        f.out = h_scal;
         CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
+        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_scal, stream));
         CR_HIP(hipStreamSynchronize(stream));
         collect_timing();
         trials += 2.0;

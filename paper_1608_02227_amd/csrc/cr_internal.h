@@ -46,7 +46,6 @@ struct cr_solver {
     // FP64 primal points eta(lam^k) (index ecur) and eta(lam^{k-1}) (index 1 - ecur)
     void *part_acc2 = nullptr, *part_col2 = nullptr;
     double *block_part = nullptr;   // per-block sums of the trial finalize
-    unsigned *ticket = nullptr;     // finished-workgroup count of the trial finalize
     unsigned timing_tick = 0;       // samples one in four trial launches for the pass timing
     double *uD[2] = {nullptr, nullptr}, *wD[2] = {nullptr, nullptr};
     double *ye[2] = {nullptr, nullptr}, *xie[2] = {nullptr, nullptr}, *dmye[2] = {nullptr, nullptr};

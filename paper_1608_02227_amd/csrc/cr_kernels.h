@@ -151,15 +151,14 @@ struct TrialFinalizeArgs {
     double *uD[2];          // Nr
     double *wD[2];          // Nr x NP
     double *block_part;     // (Nr / 16) x 4
-    // final sums, by the last workgroup to finish (fixed order): out[0..3] = column sums of
-    // block_part, out[4..7] = sums of part_red slots 0..3 over pass_blocks workgroups of the pass.
-    // `ticket` counts finished workgroups (zero before the launch; reset to zero by the last one).
-    const double *part_red;
-    int pass_blocks;
-    unsigned *ticket;
-    double *out;            // 8 doubles; may be host pinned memory
 };
 hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st);
+
+// The eight trial scalars: out[0..3] = column sums of block_part ((Nr / 16) x 4), out[4..7] = sums
+// of part_red slots 0..3 over the pass's workgroups.  Single workgroup, fixed order; `out` may be
+// pinned host memory.
+hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,
+                               hipStream_t st);
 
 
 // Accepted adaptive step: eta(lam^{k+1}) from eta(lam~^{k+1}) (yt, xit) and the adjoint of D,

@@ -1334,37 +1334,6 @@ __global__ __launch_bounds__(256) void trial_finalize_kernel(TrialFinalizeArgs a
         for (int rr = 0; rr < 16; ++rr) s += sh[rr][threadIdx.x];
         a.block_part[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
     }
-    // the last workgroup to finish reduces everything (its reads see the others' partials after
-    // the release / acquire fences around the ticket)
-    __shared__ int am_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        am_last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
-    __shared__ double red[8][256];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        double v = 0.0;
-        if (q < 4) {
-            for (int bb = threadIdx.x; bb < (int)gridDim.x; bb += 256) v += a.block_part[(size_t)bb * 4 + q];
-        } else {
-            for (int bb = threadIdx.x; bb < a.pass_blocks; bb += 256) v += a.part_red[(size_t)bb * kRed + q - 4];
-        }
-        red[q][threadIdx.x] = v;
-    }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) a.out[threadIdx.x] = red[threadIdx.x][0];
-    if (threadIdx.x == 0) *a.ticket = 0u;
 }
 
 hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st) {
@@ -1380,6 +1349,39 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
                         default: return hipErrorInvalidValue; }
     }
 #undef CR_TFIN
+    return hipGetLastError();
+}
+
+// The eight trial scalars in one single-workgroup launch, fixed order: out[q] = sum_b pa[b * 4 + q]
+// for q < 4 (the finalize's per-block sums), out[4 + q] = sum_b pb[b * kRed + q] (the pass's
+// reduction slots).  `out` may be pinned host memory (written once, read after the stream syncs).
+__global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int ba, const double *pb, int bb,
+                                                          double *out) {
+    __shared__ double sh[8][256];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double v = 0.0;
+        if (q < 4) {
+            for (int b = threadIdx.x; b < ba; b += 256) v += pa[(size_t)b * 4 + q];
+        } else {
+            for (int b = threadIdx.x; b < bb; b += 256) v += pb[(size_t)b * kRed + q - 4];
+        }
+        sh[q][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(trial_reduce_kernel, dim3(1), dim3(256), 0, st, block_part, g.Nr / 16, part_red, g.grid(),
+                       out);
     return hipGetLastError();
 }
 
