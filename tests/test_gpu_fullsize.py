@@ -188,3 +188,49 @@ def test_large_fit_N40000(cr, torch_dev):
     assert rep["dual_obj"] == pytest.approx(rep["primal_obj"] - rep["comp_sum"], rel=1e-12)
     assert rep["iters"] == 200
     assert rep["kkt"] < 1.0
+
+
+@pytest.mark.parametrize("rule", ["constant", "adaptive"])
+def test_step_parity_lse8_N2000(cr, torch_dev, rule):
+    """The N=2000, n=10 configuration (FP64): one step of the oracle from the GPU's iterates."""
+    x, ybar = W.make("lse8_N2000_n10", seed=0)
+    delta = 1e-3
+    with cr.Solver(x, ybar, delta, cr.Options(step_rule=rule, restart=False)) as s:
+        L, _, _ = s.lipschitz()
+        s.iterate(4)
+        lam4 = s.lam()
+        s.iterate(1)
+        lam5 = s.lam()
+        s5 = s.report()["step_final"]
+        s.iterate(1)
+        got = s.lam()
+        s6 = s.report()["step_final"]
+    if rule == "constant":
+        ref = _oracle_step(x, ybar, delta, L, lam5, lam4, 6)
+    else:
+        s6_ref, ref = _oracle_adaptive_step(x, ybar, delta, s5, lam5, lam4, 6)
+        assert s6 == s6_ref
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("wl,tol,precision", [("sqnorm_N200_n2", 1e-6, "fp64"), ("lse8_N2000_n10", 1e-5, "fp64"),
+                                              ("lse8_N2000_n10", 1e-4, "mixed_fp32")])
+def test_converged_config_fit_report_parity(cr, torch_dev, wl, tol, precision):
+    """A converged fit at a configuration's full size and tolerance: the oracle's stopping report
+    and certificate, evaluated on the GPU's final multipliers, agree with the GPU's report, and the
+    returned (y, xi) are the closed form of those multipliers."""
+    x, ybar = W.make(wl, seed=0)
+    delta = W.WORKLOADS[wl].delta
+    r = cr.fit(x, ybar, delta, tol, cr.Options(precision=precision), return_lambda=True, allow_noconv=False)
+    rep = r.report
+    ref = oracle.kkt_report(x, ybar, delta, r.lam)
+    assert ref["kkt"] <= tol
+    for key in ["kkt", "max_viol", "infeas_rms"]:
+        assert rep[key] == pytest.approx(ref[key], rel=1e-6, abs=1e-15), key
+    assert rep["dual_obj"] == pytest.approx(ref["dual_obj"], rel=1e-10)
+    y, xi = oracle.primal_from_dual(x, ybar, delta, r.lam)
+    assert np.max(np.abs(r.y - y)) <= 1e-10 * np.abs(y).max()
+    assert np.max(np.abs(r.xi - xi)) <= 1e-9 * max(1.0, np.abs(xi).max())
+    cert = oracle.repair_certificate(x, ybar, delta, r.lam)
+    assert rep["cert_gap"] == pytest.approx(cert["cert_gap"], rel=1e-5, abs=1e-12)
+    assert 0.0 <= rep["cert_gap"]
