@@ -5,6 +5,7 @@
 #include "cr_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -209,6 +210,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     }
     if (hipHostMalloc((void **)&s->h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return bail(CR_ENOMEM);
+    std::memset(s->h_scal, 0, 32 * sizeof(double));
     if (hipEventCreate(&s->ev_a) != hipSuccess || hipEventCreate(&s->ev_b) != hipSuccess) return bail(CR_EDEVICE);
 
     const Geometry &g = s->g;
@@ -546,8 +548,12 @@ int cr_solver::step_adaptive() {
         // h_scal (pinned host memory) receives ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b,
         // ||D_a||^2, ||D_b||^2, <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>
         CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
-        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_scal, stream));
-        CR_HIP(hipStreamSynchronize(stream));
+        const unsigned long long seq = ++trial_seq;
+        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_scal, h_seq(), seq, stream));
+        {
+            const int rc = wait_trial(seq);
+            if (rc) return rc;
+        }
         collect_timing();
         trials += 2.0;
         for (int q = 0; q < 8; ++q)
@@ -647,9 +653,30 @@ int cr_solver::step_once() {
     return CR_OK;
 }
 
-// Folds the last sampled launch into the averages (call after the stream has synchronized).
+// Waits until the trial reduction has announced sequence number `seq` in pinned memory (a spin on
+// the host: the decision is needed at once and the round trip is about half that of a stream
+// synchronization).  The stream is queried now and then, so a failed launch ends the wait.
+int cr_solver::wait_trial(unsigned long long seq) {
+    volatile unsigned long long *w = h_seq();
+    for (unsigned long spins = 1; *w != seq; ++spins) {
+        if ((spins & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(stream);
+            if (q == hipSuccess) {
+                if (*w == seq) break;
+                return fail_hip(hipErrorUnknown, "trial scalars not announced");
+            }
+            if (q != hipErrorNotReady) return fail_hip(q, "trial reduction");
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return CR_OK;
+}
+
+// Folds the last sampled launch into the averages once its end event has completed (a sample
+// still in flight is kept for a later call).
 void cr_solver::collect_timing() {
     if (!ev_pending) return;
+    if (hipEventQuery(ev_b) == hipErrorNotReady) return;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev_a, ev_b) == hipSuccess) {
         const int q = ev_pending_low ? 0 : 1;

@@ -66,7 +66,10 @@ struct cr_solver {
     double *part_red = nullptr, *part_min = nullptr;
     int *part_arg = nullptr;
     double *scal = nullptr;
-    double *h_scal = nullptr;    // pinned
+    double *h_scal = nullptr;    // pinned; h_scal[24] holds the trial sequence word
+    unsigned long long trial_seq = 0;
+    unsigned long long *h_seq() const { return reinterpret_cast<unsigned long long *>(h_scal + 24); }
+    int wait_trial(unsigned long long seq);
     std::vector<void *> owned;
 
     // iteration state

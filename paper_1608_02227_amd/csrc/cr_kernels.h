@@ -156,9 +156,10 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
 
 // The eight trial scalars: out[0..3] = column sums of block_part ((Nr / 16) x 4), out[4..7] = sums
 // of part_red slots 0..3 over the pass's workgroups.  Single workgroup, fixed order; `out` may be
-// pinned host memory.
+// pinned host memory.  If seq_out is set, `seq` is written there after the eight values are
+// visible at system scope (a host polling pinned memory may then read them).
 hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,
-                               hipStream_t st);
+                               unsigned long long *seq_out, unsigned long long seq, hipStream_t st);
 
 
 // Accepted adaptive step: eta(lam^{k+1}) from eta(lam~^{k+1}) (yt, xit) and the adjoint of D,

@@ -132,9 +132,13 @@ template <typename T> __device__ __forceinline__ T row16_sum(T v) {
 }
 
 // ---- the pair sweep -----------------------------------------------------------------------
-template <typename T, int REP, int MODE, int MB>
+// KT: residual K-steps dropped at the end (4 MB - KT steps of 4 features); the launcher passes
+// KT > 0 only when every dropped step lies beyond feature n - 1, where Xi is zero.
+template <typename T, int REP, int MODE, int MB, int KT = 0>
 __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry g) {
     constexpr int NP = 16 * MB;
+    constexpr int KS = 4 * MB - KT;                  // residual K-steps
+    static_assert(KT >= 0 && KS >= 1, "at least one residual step");
     constexpr int SX = NP + 1;                       // LDS row stride (elements): odd, no bank aliasing
     constexpr int BUF = kSuper * SX;
     constexpr int NT = 64 * kWaves;                  // threads per workgroup
@@ -313,11 +317,11 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 S[bb] = V4{0, 0, 0, 0};
                 if (kAdv) So[bb] = V4{0, 0, 0, 0};
                 if (kResidual) {
-                    // all 4 MB steps: Xi is zero beyond column n - 1, so the padded steps add zero
+                    // a fixed KS steps: Xi is zero beyond column n - 1, so padded steps add zero
                     // and the loop carries no branch (which would make the compiler drain the
                     // prefetch queue at every join)
 #pragma unroll
-                    for (int s = 0; s < 4 * MB; ++s) {
+                    for (int s = 0; s < KS; ++s) {
                         const T xa = sXb[(jl + acol + 4 * bb) * SX + 4 * s + lq];
                         S[bb] = mfma16(xa, bxi[s], S[bb]);
                         if constexpr (kAdv) So[bb] = mfma16(xa, bxio[s], So[bb]);
@@ -718,16 +722,25 @@ Geometry make_geometry(int N, int n, int slots) {
     return g;
 }
 
-template <typename T, int REP, int MODE>
-static hipError_t launch_mb(const Geometry &g, const PassArgs &a, hipStream_t st) {
+template <typename T, int REP, int MODE, int KT>
+static void launch_kt(const Geometry &g, const PassArgs &a, hipStream_t st) {
     dim3 grid(g.grid()), block(64 * kWaves);
     switch (g.MB) {
-    case 1: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 1>), grid, block, 0, st, a, g); break;
-    case 2: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 2>), grid, block, 0, st, a, g); break;
-    case 3: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 3>), grid, block, 0, st, a, g); break;
-    case 4: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 4>), grid, block, 0, st, a, g); break;
-    default: return hipErrorInvalidValue;
+    case 1: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 1, KT>), grid, block, 0, st, a, g); break;
+    case 2: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 2, KT>), grid, block, 0, st, a, g); break;
+    case 3: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 3, KT>), grid, block, 0, st, a, g); break;
+    default: hipLaunchKernelGGL((pass_kernel<T, REP, MODE, 4, KT>), grid, block, 0, st, a, g); break;
     }
+}
+
+// The per-iteration modes drop the two last residual K-steps when they hold no feature
+// (4 MB - ceil(n / 4) >= 2, e.g. n = 40: 10 of 12 steps); the other modes keep all 4 MB.
+template <typename T, int REP, int MODE>
+static hipError_t launch_mb(const Geometry &g, const PassArgs &a, hipStream_t st) {
+    if (g.MB < 1 || g.MB > kMaxMB) return hipErrorInvalidValue;
+    constexpr bool kHot = (MODE == PASS_STEP || MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS || MODE == PASS_ADV);
+    if (kHot && 4 * g.MB - g.ks1 >= 2) launch_kt<T, REP, MODE, kHot ? 2 : 0>(g, a, st);
+    else launch_kt<T, REP, MODE, 0>(g, a, st);
     return hipGetLastError();
 }
 
@@ -1356,7 +1369,8 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
 // for q < 4 (the finalize's per-block sums), out[4 + q] = sum_b pb[b * kRed + q] (the pass's
 // reduction slots).  `out` may be pinned host memory (written once, read after the stream syncs).
 __global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int ba, const double *pb, int bb,
-                                                          double *out) {
+                                                          double *out, unsigned long long *seq_out,
+                                                          unsigned long long seq) {
     __shared__ double sh[8][256];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1375,13 +1389,21 @@ __global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int
             for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x < 8) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) out[q] = sh[q][0];
+        if (seq_out) {
+            // the eight values reach system scope before the sequence word that announces them
+            __threadfence_system();
+            *reinterpret_cast<volatile unsigned long long *>(seq_out) = seq;
+        }
+    }
 }
 
 hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,
-                               hipStream_t st) {
+                               unsigned long long *seq_out, unsigned long long seq, hipStream_t st) {
     hipLaunchKernelGGL(trial_reduce_kernel, dim3(1), dim3(256), 0, st, block_part, g.Nr / 16, part_red, g.grid(),
-                       out);
+                       out, seq_out, seq);
     return hipGetLastError();
 }
 
