@@ -206,11 +206,12 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     const int arow = 4 * rg + rv;                    // feature row fed by this lane
     const int acol = CPL * rg + rv;                  // tile column fed by this lane (block 0)
 
-    // Row-constant operands: B of the residual contraction is Xi[i][4s + lq].
+    // Row-constant operands: B of the residual contraction is -Xi[i][4s + lq]; the accumulator
+    // starts at y_j + d_i - y_i, so the product leaves s_ij itself (no separate subtraction).
     T bxi[4 * MB];
 #pragma unroll
     for (int s = 0; s < 4 * MB; ++s)
-        bxi[s] = kResidual ? xi[(size_t)i * NP + 4 * s + lq] : (T)0;
+        bxi[s] = kResidual ? -xi[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmy_i = kResidual ? dmy[i] : (T)0;
     const T roff_i = (MODE == PASS_REPAIR && a.row_off) ? (T)a.row_off[i] : (T)0;
     // PASS_ADV: the previous trial's row operands (re-forming its accepted candidate)
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     T bxio[kAdv ? 4 * MB : 1];
 #pragma unroll
     for (int s = 0; s < (kAdv ? 4 * MB : 1); ++s)
-        bxio[s] = kAdv ? xio[(size_t)i * NP + 4 * s + lq] : (T)0;
+        bxio[s] = kAdv ? -xio[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmyo_i = kAdv ? static_cast<const T *>(a.dmy_o)[i] : (T)0;
 
     V4 acc[MB];
@@ -310,12 +311,17 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             // loads below the epilogue, which then waits for them)
             __builtin_amdgcn_sched_barrier(0);
 
+            const T *sYob = sYo + (kAdv ? b * kSuper : 0);
             V4 S[NB];
             V4 So[kAdv ? NB : 1];
 #pragma unroll
             for (int bb = 0; bb < NB; ++bb) {
-                S[bb] = V4{0, 0, 0, 0};
-                if (kAdv) So[bb] = V4{0, 0, 0, 0};
+                // output item v of block bb is column jc + 4 bb + v of row i
+                const int jb = jc + 4 * bb;
+                S[bb] = kResidual ? V4{sYb[jb] + dmy_i, sYb[jb + 1] + dmy_i, sYb[jb + 2] + dmy_i, sYb[jb + 3] + dmy_i}
+                                  : V4{0, 0, 0, 0};
+                if (kAdv)
+                    So[bb] = V4{sYob[jb] + dmyo_i, sYob[jb + 1] + dmyo_i, sYob[jb + 2] + dmyo_i, sYob[jb + 3] + dmyo_i};
                 if (kResidual) {
                     // a fixed KS steps: Xi is zero beyond column n - 1, so padded steps add zero
                     // and the loop carries no branch (which would make the compiler drain the
@@ -328,7 +334,6 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     }
                 }
             }
-            const T *sYob = sYo + (kAdv ? b * kSuper : 0);
 
             T out[CPL];
             T out2[kTrial ? CPL : 1];
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             for (int c = 0; c < CPL; ++c) {
                 const int j = j0 + c;
                 const bool ok = masked ? (row_ok && (j < g.N) && (j != i)) : true;
-                const T s = (sYb[jc + c] + dmy_i) - S[c >> 2][c & 3];
+                const T s = S[c >> 2][c & 3];                          // s_ij
                 if constexpr (MODE == PASS_STEP && REP == REP_F64) {
                     const T P = (T)cur.p[c], Q = (T)cur.q[c];
                     const T lt = P + bp * (P - Q);                       // lam~^k
@@ -387,12 +392,13 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
                     // re-form the accepted candidate of the previous trial: lam^k (low part)
                     const T lto = l1 + bp * (l1 - l2);
-                    const T so = (sYob[jc + c] + dmyo_i) - So[c >> 2][c & 3];
+                    const T so = So[c >> 2][c & 3];
                     T z = fmax(lto - so * invLo, -H);
                     z = ok ? z : (T)0;
                     cur.b[c >> 2][c & 3] = (float)z;                     // stored over lam^{k-2}
                     // trial from (lam^k, lam^{k-1})
-                    const T lt = z + bn * (z - l1);
+                    const T m = z - l1;
+                    const T lt = z + bn * m;
                     T la = fmax(lt - s * invL, -H);
                     T lb = fmax(lt - s * invL2, -H);
                     la = ok ? la : (T)0;
@@ -401,12 +407,14 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     out2[c] = ok ? lb - lt : (T)0;
                     tr0 += out[c] * out[c];
                     tr1 += out2[c] * out2[c];
-                    tr2 += out[c] * (la - z);                            // <D_a, cand_a - lam^k>
-                    tr3 += out2[c] * (lb - z);
+                    // cand - lam^k = D + beta m: <D, cand - lam^k> = ||D||^2 + beta <D, m>
+                    tr2 += out[c] * m;
+                    tr3 += out2[c] * m;
                 } else if constexpr (MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS) {
                     const T H = (T)hi_at<REP>(cur, c);
                     const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
-                    const T lt = l1 + bp * (l1 - l2);                    // low part of lam~^k
+                    const T m = l1 - l2;
+                    const T lt = l1 + bp * m;                            // low part of lam~^k
                     T la = fmax(lt - s * invL, -H);
                     T lb = fmax(lt - s * invL2, -H);
                     la = ok ? la : (T)0;
@@ -417,8 +425,9 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     out2[c] = ok ? lb - lt : (T)0;
                     tr0 += out[c] * out[c];
                     tr1 += out2[c] * out2[c];
-                    tr2 += out[c] * (la - l1);                           // <D_a, cand_a - lam^k>
-                    tr3 += out2[c] * (lb - l1);
+                    // cand - lam^k = D + beta m: <D, cand - lam^k> = ||D||^2 + beta <D, m>
+                    tr2 += out[c] * m;
+                    tr3 += out2[c] * m;
                 } else if constexpr (MODE == PASS_ADJ) {
                     T v;
                     if constexpr (REP == REP_F64) v = (T)cur.p[c];
@@ -464,10 +473,12 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
             if (interior) epilogue(std::false_type{});
             else epilogue(std::true_type{});
             if constexpr (kTrial && kSplit) {
+                // tr2, tr3 hold <D, m>; beta is that of the extrapolation the candidates start from
+                const double bm = kAdv ? a.beta_next : a.beta_prev;
                 red0 += (double)tr0;
                 red1 += (double)tr1;
-                red2 += (double)tr2;
-                red3 += (double)tr3;
+                red2 += (double)tr0 + bm * (double)tr2;
+                red3 += (double)tr1 + bm * (double)tr3;
             }
             {
                 const size_t e = rowoff + j0;
