@@ -113,21 +113,23 @@ template <> __device__ __forceinline__ void hi_set<REP_SPLIT_BF16>(Raw<REP_SPLIT
 
 template <typename T> __device__ __forceinline__ T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
 
-// Sum over each row of 16 lanes with DPP row shifts (pure VALU, no LDS): after shifts by 1, 2, 4
-// and 8 (lanes shifted in from outside the row read 0), lane 15 of every row holds the row total.
-template <int CTRL> __device__ __forceinline__ float dpp_shr(float v) {
+// v as seen from another lane of the same 16-lane row, selected by the DPP control CTRL (a row
+// shift reads 0 where the source lane lies outside the row).
+template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-template <int CTRL> __device__ __forceinline__ double dpp_shr(double v) {
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+// Sum over each row of 16 lanes with DPP row shifts (pure VALU, no LDS): after shifts by 1, 2, 4
+// and 8, lane 15 of every row holds the row total.
 template <typename T> __device__ __forceinline__ T row16_sum(T v) {
-    v += dpp_shr<0x111>(v);   // row_shr:1
-    v += dpp_shr<0x112>(v);   // row_shr:2
-    v += dpp_shr<0x114>(v);   // row_shr:4
-    v += dpp_shr<0x118>(v);   // row_shr:8
+    v += dpp_move<0x111>(v);   // row_shr:1
+    v += dpp_move<0x112>(v);   // row_shr:2
+    v += dpp_move<0x114>(v);   // row_shr:4
+    v += dpp_move<0x118>(v);   // row_shr:8
     return v;
 }
 
@@ -545,14 +547,30 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     acc2[mb] = *reinterpret_cast<V4 *>(&z);
                 }
             }
-            if (kAdjoint) {
-                if constexpr (!kBfAdj) {
+            if constexpr (kBfAdj) {
+                // Column sums of both differences over the wave's 16 rows as a reduce-scatter: the
+                // 16 sums (8 columns x 2 candidates) halve at each exchange (lane partners l ^ 8,
+                // l ^ 7, l ^ 2, l ^ 1, a basis of the 16 lanes), and lane lr of each lane group ends
+                // with candidate lr / 8, column lr % 8.
+                const bool h3 = (lr >> 3) & 1, h2 = (lr >> 2) & 1, h1 = (lr >> 1) & 1, h0 = lr & 1;
+                T v8[8], v4[4], v2[2];
 #pragma unroll
-                    for (int mb = 0; mb < MB; ++mb)
+                for (int q = 0; q < 8; ++q)
+                    v8[q] = (h3 ? out2[q] : out[q]) + dpp_move<0x128>(h3 ? out[q] : out2[q]);    // row_ror:8
 #pragma unroll
-                        for (int c = 0; c < CPL; ++c)
-                            acc[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out[c], acc[mb]);
-                }
+                for (int q = 0; q < 4; ++q)
+                    v4[q] = (h2 ? v8[4 + q] : v8[q]) + dpp_move<0x141>(h2 ? v8[q] : v8[4 + q]);  // row_half_mirror
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    v2[q] = (h1 ? v4[2 + q] : v4[q]) + dpp_move<0x4E>(h1 ? v4[q] : v4[2 + q]);   // lane ^ 2
+                const T v1 = (h0 ? v2[1] : v2[0]) + dpp_move<0xB1>(h0 ? v2[0] : v2[1]);         // lane ^ 1
+                (h3 ? sCol2 : sCol)[(b * kWaves + w) * kSuper + jc + (lr & 7)] = v1;
+            } else if (kAdjoint) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c)
+                        acc[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out[c], acc[mb]);
                 T cs[CPL];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) cs[c] = row16_sum(out[c]);
@@ -561,13 +579,11 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     for (int c = 0; c < CPL; ++c) sCol[(b * kWaves + w) * kSuper + jc + c] = cs[c];
                 }
                 if constexpr (kTrial) {
-                    if constexpr (!kBfAdj) {
 #pragma unroll
-                        for (int mb = 0; mb < MB; ++mb)
+                    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                            for (int c = 0; c < CPL; ++c)
-                                acc2[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out2[c], acc2[mb]);
-                    }
+                        for (int c = 0; c < CPL; ++c)
+                            acc2[mb] = mfma16(sXb[(jc + c) * SX + 16 * mb + arow], out2[c], acc2[mb]);
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) cs[c] = row16_sum(out2[c]);
                     if (lr == 15) {
