@@ -67,7 +67,8 @@ def pass_kernel(rule: str, precision: str) -> str:
         mode = "PASS_TRIAL" if precision == "fp64" else "PASS_ADV"
     else:
         mode = "PASS_STEP"
-    return f"pass_kernel<{_REP[precision]},{mode},MB=3>"
+    # n = 40: three 16-feature blocks; the per-iteration passes run 10 of the 12 residual K-steps
+    return f"pass_kernel<{_REP[precision]},{mode},MB=3,KT=2>"
 
 
 def step_kernel_stats(rep: dict, precision: str, rule: str) -> dict:

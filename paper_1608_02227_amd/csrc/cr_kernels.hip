@@ -1323,18 +1323,19 @@ hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit,
 
 // Both candidates of a trial pass: adjoints (A1^T D_q, A2^T D_q) from the pass partials, like the
 // power-mode finalize, plus per-block sums of ||A1^T D_q||^2 and ||A2^T D_q||^2 (4 per block).
+// The two candidates run in the two halves of the workgroup (threads 0-255 and 256-511).
 template <typename T, int MB>
-__global__ __launch_bounds__(256) void trial_finalize_kernel(TrialFinalizeArgs a, Geometry g) {
+__global__ __launch_bounds__(512) void trial_finalize_kernel(TrialFinalizeArgs a, Geometry g) {
     constexpr int NP = 16 * MB;
+    const int q = threadIdx.x >> 8;
     const int t = threadIdx.x & 15;
-    const int r = threadIdx.x >> 4;
+    const int r = (threadIdx.x & 255) >> 4;
     const int i = blockIdx.x * 16 + r;
     const bool valid = i < g.N;
     __shared__ double sh[16][4];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const T *pacc = static_cast<const T *>(a.part_acc[q]);
-        const T *pcol = static_cast<const T *>(a.part_col[q]);
+    {
+        const T *pacc = static_cast<const T *>(q ? a.part_acc[1] : a.part_acc[0]);
+        const T *pcol = static_cast<const T *>(q ? a.part_col[1] : a.part_col[0]);
         double lx[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
@@ -1358,12 +1359,12 @@ __global__ __launch_bounds__(256) void trial_finalize_kernel(TrialFinalizeArgs a
             const int m = 16 * mb + t;
             double v = 0.0;
             if (valid && m < g.n) v = rsum * a.xf[(size_t)i * NP + m] - lx[mb];
-            a.wD[q][(size_t)i * NP + m] = v;
+            (q ? a.wD[1] : a.wD[0])[(size_t)i * NP + m] = v;
             wsq += v * v;
         }
         for (int m = 1; m < 16; m <<= 1) wsq += __shfl_xor(wsq, m, 16);
         if (t == 0) {
-            a.uD[q][i] = u;
+            (q ? a.uD[1] : a.uD[0])[i] = u;
             sh[r][2 * q] = u * u;
             sh[r][2 * q + 1] = wsq;
         }
@@ -1377,7 +1378,7 @@ __global__ __launch_bounds__(256) void trial_finalize_kernel(TrialFinalizeArgs a
 }
 
 hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st) {
-    dim3 grid(g.Nr / 16), block(256);
+    dim3 grid(g.Nr / 16), block(512);
 #define CR_TFIN(T, MBV) hipLaunchKernelGGL((trial_finalize_kernel<T, MBV>), grid, block, 0, st, a, g)
     if (fp32) {
         switch (g.MB) { case 1: CR_TFIN(float, 1); break; case 2: CR_TFIN(float, 2); break;
