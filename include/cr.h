@@ -84,7 +84,11 @@ typedef struct {
     int32_t stop_rule;       /* 0 (default): stop when report.kkt <= tol; 1: stop when the certified
                                 gap report.cert_gap <= tol, i.e. the multipliers are tol-optimal for
                                 the dual (the inner test of the continuation, Section 2.4.1) */
-    int32_t reserved[2];
+    int32_t check_rule;      /* 1 (default): after a test that improved on the previous one, the next
+                                comes where a geometric decay through the two would reach tol, but
+                                no sooner than check_every / 5 (at least 1) and no later than
+                                check_every iterations; 0: a test every check_every iterations */
+    int32_t reserved[1];
 } cr_options;
 
 typedef struct {

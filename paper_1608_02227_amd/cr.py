@@ -39,7 +39,8 @@ class CROptions(C.Structure):
         ("upsilon", C.c_double),
         ("restart", C.c_int32),
         ("stop_rule", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("check_rule", C.c_int32),
+        ("reserved", C.c_int32 * 1),
     ]
 
 
@@ -198,6 +199,8 @@ class Options:
     upsilon: float = 2.0
     restart: bool = True            # adaptive step: gradient momentum restart (not in the paper)
     stop: str = "kkt"               # "kkt": report.kkt <= tol; "gap": certified gap <= tol
+    checks: str = "predict"         # "predict": next test at the extrapolated crossing of tol,
+                                    # within [check_every / 5, check_every]; "fixed": every check_every
 
     def to_c(self) -> CROptions:
         o = CROptions()
@@ -218,6 +221,7 @@ class Options:
         o.upsilon = self.upsilon
         o.restart = 1 if self.restart else 0
         o.stop_rule = {"kkt": 0, "gap": 1}[self.stop]
+        o.check_rule = {"fixed": 0, "predict": 1}[self.checks]
         return o
 
 

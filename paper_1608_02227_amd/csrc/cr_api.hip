@@ -70,6 +70,7 @@ extern "C" void cr_default_options(cr_options *opt) {
     opt->step_rule = 1;
     opt->upsilon = 2.0;
     opt->restart = 1;
+    opt->check_rule = 1;
 }
 
 extern "C" const char *cr_strerror(int code) {
@@ -152,6 +153,7 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->step_rule == 1 && !(opt->upsilon > 1.0 && std::isfinite(opt->upsilon))) return CR_EINVAL;
         if (opt->restart < 0 || opt->restart > 1) return CR_EINVAL;
         if (opt->stop_rule < 0 || opt->stop_rule > 1) return CR_EINVAL;
+        if (opt->check_rule < 0 || opt->check_rule > 1) return CR_EINVAL;
     }
     return CR_OK;
 }
@@ -886,6 +888,8 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
     const bool trace = getenv("CR_TRACE") != nullptr;
     // iteration 0 check: lam^0 may already be optimal (e.g. convex data)
     const bool by_gap = opt.stop_rule == 1;
+    double prev_r = -1.0;        // residual and iteration of the previous test (check_rule 1)
+    int64_t prev_k = -1;
     for (;;) {
         int rc = check(&rep, by_gap);
         ++checks;
@@ -913,7 +917,21 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
             rc = refresh_eta(true);   // exact FP64 eta(lam^k), eta(lam^{k-1}) after the test
             if (rc) return rc;
         }
-        const int64_t todo = std::min<int64_t>(opt.check_every, kmax - k);
+        int64_t gap = opt.check_every;
+        if (opt.check_rule == 1) {
+            // after progress, aim the next test at the iteration where the decay seen between the
+            // last two tests would reach tol (clamped to [check_every / 5, check_every])
+            const double r = by_gap ? rep.cert_gap : rep.kkt;
+            if (prev_r > 0.0 && r > 0.0 && r < prev_r && k > prev_k) {
+                const double rate = std::log(prev_r / r) / (double)(k - prev_k);
+                const double m = std::ceil(std::log(r / tol) / rate);
+                const int64_t lo = std::max<int64_t>(1, opt.check_every / 5);
+                gap = m < (double)opt.check_every ? std::max<int64_t>(lo, (int64_t)m) : opt.check_every;
+            }
+            prev_r = r;
+            prev_k = k;
+        }
+        const int64_t todo = std::min<int64_t>(gap, kmax - k);
         for (int64_t q = 0; q < todo; ++q) {
             rc = adaptive ? step_adaptive() : step_once();
             if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }

@@ -150,7 +150,7 @@ def _golden(name):
 def test_converged_fit_fp64_matches_oracle(cr, torch_dev, name, ybar_rel):
     gd = _golden(name)
     x, ybar = W.make(gd["workload"], seed=gd["seed"], N=gd["N"])
-    opt = cr.Options(L=gd["L"], check_every=gd["check_every"], step_rule="constant")
+    opt = cr.Options(L=gd["L"], check_every=gd["check_every"], step_rule="constant", checks="fixed")
     r = cr.fit(x, ybar, gd["delta"], gd["tol"], opt, allow_noconv=False)
     assert r.report["kkt"] <= gd["tol"]
     y_ref = np.array(gd["y"])
@@ -173,7 +173,8 @@ def test_fp64_fit_values_at_5000_iterations(cr, torch_dev):
 def test_converged_fit_mixed_matches_oracle(cr, torch_dev, precision):
     gd = _golden("lse8_N400_n10_seed1_tol1e-4")
     x, ybar = W.make(gd["workload"], seed=gd["seed"], N=gd["N"])
-    opt = cr.Options(precision=precision, L=gd["L"], check_every=gd["check_every"], step_rule="constant")
+    opt = cr.Options(precision=precision, L=gd["L"], check_every=gd["check_every"], step_rule="constant",
+                     checks="fixed")
     r = cr.fit(x, ybar, gd["delta"], gd["tol"], opt, allow_noconv=False)
     assert r.report["kkt"] <= gd["tol"]
     assert _rel(r.y, np.array(gd["y"])) <= 1e-4
@@ -258,7 +259,8 @@ def test_adaptive_iterates_mixed_match_oracle(cr, torch_dev, precision, restart)
 def test_converged_adaptive_fit_fp64_matches_oracle(cr, torch_dev, name):
     gd = _golden(name)
     x, ybar = W.make(gd["workload"], seed=gd["seed"], N=gd["N"])
-    opt = cr.Options(L=gd["L"], check_every=gd["check_every"], upsilon=gd["upsilon"], restart=gd["restart"])
+    opt = cr.Options(L=gd["L"], check_every=gd["check_every"], upsilon=gd["upsilon"], restart=gd["restart"],
+                     checks="fixed")
     r = cr.fit(x, ybar, gd["delta"], gd["tol"], opt, allow_noconv=False)
     assert r.report["kkt"] <= gd["tol"]
     # iteration counts move with the trajectory (a 1e-15 change of ybar turns the oracle's 3,250
@@ -283,10 +285,28 @@ def test_converged_adaptive_fit_fp64_matches_oracle(cr, torch_dev, name):
 def test_converged_adaptive_fit_mixed_matches_oracle(cr, torch_dev, precision):
     gd = _golden("restart_lse8_N400_n10_seed1_tol1e-7")
     x, ybar = W.make(gd["workload"], seed=gd["seed"], N=gd["N"])
-    opt = cr.Options(precision=precision, L=gd["L"], check_every=gd["check_every"])
+    opt = cr.Options(precision=precision, L=gd["L"], check_every=gd["check_every"], checks="fixed")
     r = cr.fit(x, ybar, gd["delta"], 1e-4, opt, allow_noconv=False)
     assert r.report["kkt"] <= 1e-4
     assert _rel(r.y, np.array(gd["y"])) <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_predicted_test_schedule(cr, torch_dev, precision):
+    """The predictive stopping-test schedule changes when the FP64 tests run, never what they
+    certify: the fit stops at a test whose report meets tol, the oracle's report on the returned
+    multipliers agrees, and the tests come at most check_every apart."""
+    x, ybar = W.make("lse8_N2000_n10", seed=1, N=400)
+    delta, tol = 1e-3, 1e-5
+    fixed = cr.fit(x, ybar, delta, tol, cr.Options(precision=precision, checks="fixed"), allow_noconv=False)
+    pred = cr.fit(x, ybar, delta, tol, cr.Options(precision=precision, checks="predict"), allow_noconv=False,
+                  return_lambda=True)
+    assert fixed.report["iters"] % 50 == 0
+    assert pred.report["kkt"] <= tol
+    # a test every check_every at most: at least iters / 50 tests besides the one at k = 0
+    assert pred.report["checks"] >= pred.report["iters"] // 50 + 1
+    ref = oracle.kkt_report(x, ybar, delta, pred.lam)
+    assert ref["kkt"] == pytest.approx(pred.report["kkt"], rel=1e-6)
 
 
 def test_fit_device_pointers_match_host(cr, torch_dev):
