@@ -64,7 +64,7 @@ typedef struct {
     double L;                /* > 0: use this Lipschitz constant; 0: power iteration (default) */
     int32_t power_max_iters; /* power-iteration cap; default 300 */
     double power_rtol;       /* power-iteration relative stopping change; 0 (default): 1e-8 with the
-                                constant step, 1e-4 with the adaptive step (which only starts from
+                                constant step, 1e-2 with the adaptive step (which only starts from
                                 s_0 = L and checks every step) */
     int32_t momentum;        /* 1: P-APG (default); 0: plain projected dual gradient ascent */
     int32_t certificate;     /* 1: compute the feasible repair and certified gap (default 1) */

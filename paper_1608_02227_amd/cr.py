@@ -189,7 +189,7 @@ class Options:
     time_budget_s: float = 0.0
     L: float = 0.0
     power_max_iters: int = 300
-    power_rtol: float = 0.0         # 0: 1e-8 (constant step) / 1e-4 (adaptive step)
+    power_rtol: float = 0.0         # 0: 1e-8 (constant step) / 1e-2 (adaptive step)
     momentum: bool = True
     certificate: bool = True
     device: int = 0

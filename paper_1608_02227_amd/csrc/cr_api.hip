@@ -61,7 +61,7 @@ extern "C" void cr_default_options(cr_options *opt) {
     opt->time_budget_s = 0.0;
     opt->L = 0.0;
     opt->power_max_iters = 300;
-    opt->power_rtol = 0.0;   // automatic: 1e-8 for the constant step, 1e-4 for the adaptive one
+    opt->power_rtol = 0.0;   // automatic: 1e-8 for the constant step, 1e-2 for the adaptive one
     opt->momentum = 1;
     opt->certificate = 1;
     opt->device = 0;
@@ -692,8 +692,8 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
     const double t0 = now_s();
     CR_HIP(hipSetDevice(device));
     // The constant step 1/L needs L itself; the adaptive rule only starts from s_0 = L and checks
-    // every step, so a coarser estimate serves it.
-    const double rtol = opt.power_rtol > 0.0 ? opt.power_rtol : (adaptive ? 1e-4 : 1e-8);
+    // every step (an estimate a few percent low costs at most one retry pass at the start).
+    const double rtol = opt.power_rtol > 0.0 ? opt.power_rtol : (adaptive ? 1e-2 : 1e-8);
     // Mixed modes run the power passes in FP32 when the tolerance is far above FP32 resolution
     // (the FP64 vector is normalized each step and re-rounded, so errors do not accumulate).
     const bool f32 = fp32pass && rtol >= 1e-6;

@@ -79,15 +79,17 @@ def test_lipschitz_matches_oracle(cr, torch_dev, wl, N, seed):
 
 @pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
 def test_lipschitz_mixed_coarse(cr, torch_dev, precision):
-    # adaptive step, default tolerance 1e-4: FP32 power passes; the estimate (from below) stays
-    # within the tolerance's reach of the oracle's converged value
+    # adaptive step, default tolerance 1e-2: FP32 power passes; the estimate comes from below and,
+    # at the same tolerance, matches the oracle's (same start vector and stopping rule)
     x, ybar = W.make("quad_N8000_n40", seed=2, N=250)
     L0, _, _ = oracle.lipschitz(x, 1e-3)
+    L1, _, it1 = oracle.lipschitz(x, 1e-3, rtol=1e-2)
     with cr.Solver(x, ybar, 1e-3, cr.Options(precision=precision)) as s:
         L, _, it = s.lipschitz()
-    assert L == pytest.approx(L0, rel=2e-3)
     assert L <= L0 * (1 + 1e-5)
-    assert it < 300
+    assert abs(it - it1) <= 2
+    # same stopping iteration: FP32 rounding only; one iteration apart: at most the tolerance
+    assert L == pytest.approx(L1, rel=1e-5 if it == it1 else 2e-2)
 
 
 @pytest.mark.parametrize("wl,N,seed,momentum", [("sqnorm_N200_n2", 200, 0, True), ("lse8_N2000_n10", 150, 1, True),
