@@ -484,6 +484,7 @@ int cr_solver::materialize() {
 //     ||A1^T D||^2 + ||A2^T D||^2 / delta <= s ||D||^2,
 // which the pass provides directly (adjoint of D and ||D||^2) without differencing dual values.
 int cr_solver::step_adaptive() {
+    test_fresh = false;
     if (!primed) {
         int rc = prime();
         if (rc) return rc;
@@ -606,6 +607,7 @@ int cr_solver::step_adaptive() {
 }
 
 int cr_solver::step_once() {
+    test_fresh = false;
     if (!primed) {
         int rc = prime();
         if (rc) return rc;
@@ -689,6 +691,7 @@ void cr_solver::collect_timing() {
 }
 
 int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
+    test_fresh = false;   // the power passes reuse scal and the pass arrays
     const double t0 = now_s();
     CR_HIP(hipSetDevice(device));
     // The constant step 1/L needs L itself; the adaptive rule only starts from s_0 = L and checks
@@ -743,18 +746,24 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
 
 // FP64 stopping test at lam^k; fills rep (without timing fields).  Leaves eta(lam^k) in yc/xic.
 int cr_solver::check(cr_report *rep_out, bool certificate) {
-    int rc = rebase();
-    if (rc) return rc;
-    rc = adjoint_to(cur, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
-    if (rc) return rc;
-    PassArgs a{};
-    a.lam_h = lam_hi;
-    a.lam_a = lam[cur];
-    a.xhat = xhat64; a.xi = xic; a.yv = yc; a.dmy = dmyc;
-    a.part_red = part_red;
-    CR_HIP(launch_pass(g, PASS_KKT, false, this->rep, a, stream));
-    CR_HIP(launch_reduce(part_red, g.grid(), kRed, 2, 4, scal, stream));
-    CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 4, stream));
+    // the certificate right after a test at the same iterate (the end of a fit) reuses that test's
+    // adjoint and KKT reductions
+    const bool reuse = certificate && test_fresh && checked_k == k && !pend;
+    if (!reuse) {
+        int rc = rebase();
+        if (rc) return rc;
+        rc = adjoint_to(cur, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
+        if (rc) return rc;
+        PassArgs a{};
+        a.lam_h = lam_hi;
+        a.lam_a = lam[cur];
+        a.xhat = xhat64; a.xi = xic; a.yv = yc; a.dmy = dmyc;
+        a.part_red = part_red;
+        CR_HIP(launch_pass(g, PASS_KKT, false, this->rep, a, stream));
+        CR_HIP(launch_reduce(part_red, g.grid(), kRed, 2, 4, scal, stream));
+        CR_HIP(launch_reduce(rowred, g.Nr, 2, 0, 2, scal + 4, stream));
+    }
+    test_fresh = false;
     int nsc = 6;
     if (certificate) {
         PassArgs r{};
@@ -834,10 +843,12 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
     for (int q = 0; q < nsc; ++q) finite = finite && std::isfinite(h_scal[q]);
     rep_out->status = finite ? CR_OK : CR_ENUMERIC;
     checked_k = k;
+    test_fresh = finite;
     return finite ? CR_OK : CR_ENUMERIC;
 }
 
 int cr_solver::promote() {
+    test_fresh = false;
     if (rep == REP_F64) return CR_OK;
     CR_HIP(hipSetDevice(device));
     int rc0 = materialize();
@@ -965,6 +976,7 @@ extern "C" int cr_solver_set_delta(cr_solver *s, double delta) {
     int rc = s->materialize();
     if (rc) return rc;
     s->delta = delta;
+    s->test_fresh = false;
     s->L = s->sigma2 > 0.0 ? s->sigma2 / delta : 0.0;   // L_gamma = sigma_max(C)^2 / gamma
     s->s_step = s->L;
     s->t = 1.0;                                         // a fresh P-APG run from the current lam

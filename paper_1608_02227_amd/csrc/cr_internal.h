@@ -76,6 +76,9 @@ struct cr_solver {
     double L = 0.0, sigma2 = 0.0, preprocess_s = 0.0;
     int power_iters = 0;
     int64_t k = 0, k_low = 0, checked_k = -1;
+    // the last stopping test's device results (eta(lam^k) in yc / xic / dmyc, the KKT reductions in
+    // scal[0..5]) still describe the current iterate; cleared by anything that moves it
+    bool test_fresh = false;
     int cur = 0;                 // buffer holding lam^k
     double t = 1.0;              // t_{k+1}
     double beta_last = 0.0;      // beta_k (0 before the first iteration)
