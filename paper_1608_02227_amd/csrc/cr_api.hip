@@ -201,6 +201,8 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     double ymin = hy[0], ymax = hy[0];
     for (double v : hy) { ymin = std::min(ymin, v); ymax = std::max(ymax, v); }
     s->scale = std::max(1.0, ymax - ymin);
+    s->yrange = ymax - ymin;
+    s->lam_zero = (lambda0 == nullptr);
 
     auto bail = [&](int code) { delete s; return code; };
     if (opt.stream) {
@@ -485,6 +487,7 @@ int cr_solver::materialize() {
 // which the pass provides directly (adjoint of D and ||D||^2) without differencing dual values.
 int cr_solver::step_adaptive() {
     test_fresh = false;
+    lam_zero = false;
     if (!primed) {
         int rc = prime();
         if (rc) return rc;
@@ -608,6 +611,7 @@ int cr_solver::step_adaptive() {
 
 int cr_solver::step_once() {
     test_fresh = false;
+    lam_zero = false;
     if (!primed) {
         int rc = prime();
         if (rc) return rc;
@@ -897,11 +901,23 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
     int checks = 0;
     const int64_t kmax = opt.max_iters;
     const bool trace = getenv("CR_TRACE") != nullptr;
-    // iteration 0 check: lam^0 may already be optimal (e.g. convex data)
+    // iteration 0 check: lam^0 may already be optimal (e.g. constant data)
     const bool by_gap = opt.stop_rule == 1;
     double prev_r = -1.0;        // residual and iteration of the previous test (check_rule 1)
     int64_t prev_k = -1;
     for (;;) {
+        // At the zero start every pair has s_ij = ybar_j - ybar_i, so the natural residual is
+        // (max ybar - min ybar) / scale: when that exceeds tol the test cannot pass and is skipped.
+        if (k == 0 && lam_zero && !by_gap && yrange / scale > tol && kmax > 0) {
+            int rc = CR_OK;
+            for (int64_t q = 0; q < std::min<int64_t>(opt.check_every, kmax); ++q) {
+                rc = adaptive ? step_adaptive() : step_once();
+                if (rc) break;
+            }
+            if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
+            if (rc) return rc;
+            continue;
+        }
         int rc = check(&rep, by_gap);
         ++checks;
         if (trace)

@@ -79,6 +79,9 @@ struct cr_solver {
     // the last stopping test's device results (eta(lam^k) in yc / xic / dmyc, the KKT reductions in
     // scal[0..5]) still describe the current iterate; cleared by anything that moves it
     bool test_fresh = false;
+    // lam is still the zero start: its stopping report is known in closed form (below)
+    bool lam_zero = true;
+    double yrange = 0.0;         // max ybar - min ybar
     int cur = 0;                 // buffer holding lam^k
     double t = 1.0;              // t_{k+1}
     double beta_last = 0.0;      // beta_k (0 before the first iteration)

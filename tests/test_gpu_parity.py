@@ -305,8 +305,8 @@ def test_predicted_test_schedule(cr, torch_dev, precision):
                   return_lambda=True)
     assert fixed.report["iters"] % 50 == 0
     assert pred.report["kkt"] <= tol
-    # a test every check_every at most: at least iters / 50 tests besides the one at k = 0
-    assert pred.report["checks"] >= pred.report["iters"] // 50 + 1
+    # a test every check_every at most (the one at k = 0 is skipped when it cannot pass)
+    assert pred.report["checks"] >= pred.report["iters"] // 50
     ref = oracle.kkt_report(x, ybar, delta, pred.lam)
     assert ref["kkt"] == pytest.approx(pred.report["kkt"], rel=1e-6)
 
