@@ -381,8 +381,12 @@ int cr_solver::adjoint_to(int idx, double *y, double *xi, double *dmy, bool with
 }
 
 // Split representations: fold lam^k's low part into the shared high part (H <- round(H + l_k)),
-// re-express both low parts against it and cache the FP64 adjoint C^T H for the next steps.
-int cr_solver::rebase() {
+// re-express both low parts against it and, in the same pass, form an FP64 adjoint: of H for
+// the constant step (cached for its next steps), of lam^k itself for the adaptive one (its
+// eta(lam^k), with the row terms of the stopping report, lands in yc / xic / dmyc).
+// Returns with eta_in_yc telling which.
+int cr_solver::rebase(bool *eta_in_yc) {
+    if (eta_in_yc) *eta_in_yc = false;
     int rc = materialize();
     if (rc) return rc;
     if (rep == REP_F64) return CR_OK;
@@ -393,16 +397,25 @@ int cr_solver::rebase() {
     a.xhat = xhat64;
     a.part_acc = part_acc;
     a.part_col = part_col;
+    a.rebase_lam = adaptive ? 1 : 0;
     CR_HIP(launch_pass(g, PASS_REBASE, false, rep, a, stream));
     FinalizeArgs f{};
     f.part_acc = part_acc;
     f.part_col = part_col;
     f.xf = xhat64;
     f.ybar = ybar64;
-    f.y = ubase; f.xi = wbase; f.dmy = dmyr;
-    f.inv_delta = 1.0;
-    f.power = 1;
+    if (adaptive) {
+        f.y = yc; f.xi = xic; f.dmy = dmyc;
+        f.rowred = rowred;
+        f.inv_delta = 1.0 / delta;
+        f.power = 0;
+    } else {
+        f.y = ubase; f.xi = wbase; f.dmy = dmyr;
+        f.inv_delta = 1.0;
+        f.power = 1;
+    }
     CR_HIP(launch_finalize(g, false, f, stream));
+    if (eta_in_yc) *eta_in_yc = adaptive;
     return CR_OK;
 }
 
@@ -754,10 +767,13 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
     // adjoint and KKT reductions
     const bool reuse = certificate && test_fresh && checked_k == k && !pend;
     if (!reuse) {
-        int rc = rebase();
+        bool have_eta = false;
+        int rc = rebase(&have_eta);
         if (rc) return rc;
-        rc = adjoint_to(cur, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
-        if (rc) return rc;
+        if (!have_eta) {
+            rc = adjoint_to(cur, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+        }
         PassArgs a{};
         a.lam_h = lam_hi;
         a.lam_a = lam[cur];

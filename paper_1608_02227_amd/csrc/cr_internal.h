@@ -100,7 +100,7 @@ struct cr_solver {
     void release(void *p);
     int adjoint_to(int idx, double *y, double *xi, double *dmy, bool with_rowred, float *y32_, float *xi32_,
                    float *dmy32_);
-    int rebase();
+    int rebase(bool *eta_in_yc = nullptr);
     int prime();
     int step_once();
     int step_adaptive();

@@ -25,7 +25,8 @@ enum PassMode : int {
     PASS_REPAIR = 4, // column minima of s and their arg-min rows (max-affine repair)
     PASS_RESID = 5,  // writes s = C eta (FP64, zero diagonal and padding) into lam_b
     PASS_REBASE = 6, // split forms: H <- round(H + l_k), both low parts re-expressed against the
-                     // new H, and the FP64 adjoint of the new H (cached for the next steps)
+                     // new H, and the FP64 adjoint of the new H (cached for the constant step) or,
+                     // with rebase_lam, of lam^k
     PASS_TRIAL = 7,  // adaptive step: two Step-2 candidates lam~ - s / s_a and lam~ - s / s_b from
                      // one read of the iterates, written to lam_c / lam_d, with the adjoints of
                      // D = candidate - lam~ (part_acc / part_acc2), ||D||^2 (part_red slots 0, 1)
@@ -114,6 +115,9 @@ struct PassArgs {
     // PASS_REPAIR only (optional): per-row offsets c_i; the pass then takes column minima of
     // s_ij - c_i (the relaxation rounds of the own-slope repair)
     const double *row_off;
+    // PASS_REBASE only: 0 accumulates the adjoint of the new high part H', 1 that of lam^k as
+    // stored after the re-basing (H' + l_k')
+    int rebase_lam;
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,

@@ -1,20 +1,22 @@
 // gfx950 kernels for the dual-smoothing (P-APG) convex-regression fit.
 //
-// The hot loop is one sweep over all N^2 pairs per iteration (pass_kernel, mode PASS_STEP).
-// A workgroup owns 64 rows i (four waves of 16) and one chunk of columns j.  For every tile of
-// 16 columns a wave
-//   1. forms the transposed residual tile S^T = X_J Xi_I^T with FP64 (or FP32) MFMA 16x16x4,
-//      so each lane holds 4 consecutive columns j of one row i;
-//   2. reads lam^{k-1} and lam^{k-2} for those 4 pairs (32 contiguous bytes in FP64), forms
-//      lam~^k, s_ij = y_j - y_i + xi_i^T x_i - xi_i^T x_j, the projected step lam^k and the
-//      next extrapolated point lam~^{k+1}, and writes lam^k over lam^{k-2};
-//   3. feeds lam~^{k+1} straight back into a second MFMA, (Lam~ Xhat)_I += Lam~_IJ Xhat_J,
+// The hot loop is one sweep over all N^2 pairs per iteration (pass_kernel).  A workgroup owns
+// 128 rows i (eight waves of 16) and one chunk of columns j.  For every tile of 16 rows x 16
+// (FP64 state) or 32 (split state) columns a wave
+//   1. forms the transposed residual tile S^T = X_J Xi_I^T with FP64 (or FP32) MFMA 16x16x4, the
+//      accumulator starting at y_j + d_i - y_i so that it ends as s_ij; each lane holds 4 (or 8)
+//      consecutive columns j of one row i;
+//   2. reads the stored iterates for those pairs (whole 128-byte lines per lane group), forms
+//      lam~^k, the projected step(s) and the next extrapolated point, and writes lam^k over the
+//      older iterate;
+//   3. feeds the result straight back into a second MFMA, (Lam~ Xhat)_I += Lam~_IJ Xhat_J,
 //      where Xhat carries a column of ones so that the same product yields the row sums;
 //   4. reduces the column sums of the tile across the 16 lanes of each lane group.
 // The multipliers are therefore read twice and written once per iteration (the HBM floor
 // of a two-state momentum method); X tiles are staged once per workgroup in LDS.  Column
-// sums and (Lam X) rows leave the workgroup as partials that finalize_kernel reduces in a
-// fixed order, so every iteration is bitwise reproducible.
+// sums and (Lam X) rows leave the workgroup as partials that the finalize kernels reduce in a
+// fixed order, so every iteration is bitwise reproducible.  The adaptive step's trial passes
+// (PASS_TRIAL, PASS_TRIAL_NS, PASS_ADV) evaluate two candidate steps per sweep the same way.
 
 #include "cr_internal.h"
 
@@ -199,6 +201,7 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
     const int nsup = (cend - cbeg) / kSuper;
     const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L, invL2 = (T)a.inv_L2;
     const T invLo = (T)a.inv_Lo;
+    const bool rebase_lam = (MODE == PASS_REBASE) && a.rebase_lam != 0;
     // Output rows of the 16x16x4 MFMA: lane group g, item v receives row 4 g + v in the FP32 form
     // and row 4 v + g in the FP64 form.  A-row rho is therefore fed the source that lane group
     // g(rho), item v(rho) must see: feature 16 mb + 4 g + v in the adjoint contraction, column
@@ -445,7 +448,8 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                     cur.a[c >> 2][c & 3] = ok ? (float)(lam0 - Hn) : 0.f;
                     cur.b[c >> 2][c & 3] = ok ? (float)(lam1 - Hn) : 0.f;
                     hi_set<REP>(cur, c, (float)Hn);
-                    out[c] = (T)Hn;
+                    // the adjoint of H' (cached for the constant step) or of lam^k as now stored
+                    out[c] = rebase_lam ? (T)(Hn + (double)cur.a[c >> 2][c & 3]) : (T)Hn;
                 } else if constexpr (MODE == PASS_POWER) {
                     const T z = ok ? s : (T)0;
                     out[c] = z;
