@@ -195,28 +195,64 @@ def run_continuation(cr, W, T: int, precision: str) -> dict:
             "seconds_host_arrays": round(dt, 3), "steps": steps}
 
 
-def run_large(cr, W, iters: int, precision: str, rule: str, restart: bool) -> dict:
-    """K iterations of the N=40000, n=20 fit (the largest workload; 1.6e9 pairs)."""
+def run_large(cr, W, cap: int, tol: float, precision: str, rule: str, restart: bool) -> dict:
+    """The N=40000, n=20 fit (the largest workload; 1.6e9 pairs) to the KKT tolerance, at most `cap`
+    iterations or 90 s."""
     name = "maxaff16_N40000_n20"
     wl = W.WORKLOADS[name]
     x, yb = W.make(name, seed=0)
-    with cr.Solver(x, yb, wl.delta, cr.Options(precision=precision, step_rule=rule, restart=restart)) as s:
+    opt = cr.Options(precision=precision, step_rule=rule, restart=restart, max_iters=cap, time_budget_s=90.0)
+    with cr.Solver(x, yb, wl.delta, opt) as s:
         t0 = time.perf_counter()
         L, _, pit = s.lipschitz()
         t1 = time.perf_counter()
-        s.iterate(iters)
+        code, rep = s.solve(tol)
         t2 = time.perf_counter()
-        rep = s.report()
+    iters = rep["iters"]
     ms = rep["step_ms_low"] if precision != "fp64" else rep["step_ms_fp64"]
     pairs = wl.N * (wl.N - 1)
     gbs = PASS_BYTES[(rule, precision)] * pairs / (ms * 1e-3) / 1e9 if ms > 0 else None
-    log(f"large fit: {iters} iterations in {t2 - t1:.2f} s, pass {ms:.3f} ms, {gbs:.0f} GB/s")
+    log(f"large fit: {iters} iterations to KKT {rep['kkt']:.2e} in {t2 - t0:.2f} s, pass {ms:.3f} ms, {gbs:.0f} GB/s")
     return {"workload": f"{name}: x~N(0,I_20), f0=max of 16 affine + 0.1||x||^2, eps~N(0,0.3^2), delta=1e-3",
-            "N": wl.N, "n": wl.n, "precision": precision, "step_rule": rule, "restart": restart, "iters": iters,
+            "N": wl.N, "n": wl.n, "precision": precision, "step_rule": rule, "restart": restart, "tol": tol,
+            "status": code, "iters": iters, "kkt": rep["kkt"], "y_err_bound": rep["y_err_bound"],
+            "time_to_tol_s": round(t2 - t0, 3), "preprocess_s": round(t1 - t0, 3), "power_iters": pit,
             "trial_passes": int(rep["trials"] / 2) if rule == "adaptive" else iters,
-            "dual_iters_per_s": round(iters / (t2 - t1), 1), "preprocess_s": round(t1 - t0, 3),
-            "power_iters": pit, "pass_ms": round(ms, 4), "pass_hbm_gbs": round(gbs, 1) if gbs else None,
-            "pass_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "kkt_after": rep["kkt"]}
+            "dual_iters_per_s": round(iters / (t2 - t1), 1),
+            "pass_ms": round(ms, 4), "pass_hbm_gbs": round(gbs, 1) if gbs else None,
+            "pass_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4) if gbs else None}
+
+
+def run_configs(cr, W, torch, rule: str, restart: bool) -> list:
+    """The two small configurations, FP64 and mixed-FP32, each fitted to its tolerance (second of two
+    runs timed): N=200, n=2 (KKT 1e-6) and N=2000, n=10 (KKT 1e-4); the mixed fit's fitted values
+    against the FP64 fit's."""
+    rows = []
+    for name, N, tol in [("sqnorm_N200_n2", 200, 1e-6), ("lse8_N2000_n10", 2000, 1e-4)]:
+        wl = W.WORKLOADS[name]
+        x, yb = W.make(name, seed=0, N=N)
+        xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(yb).cuda()
+        res = {}
+        for prec in ["fp64", "mixed_fp32"]:
+            opt = cr.Options(precision=prec, step_rule=rule, restart=restart)
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = cr.fit(xd, yd, wl.delta, tol, opt)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            res[prec] = (r, dt)
+        y64 = res["fp64"][0].y
+        row = {"workload": name, "N": N, "n": wl.n, "tol": tol}
+        for prec, (r, dt) in res.items():
+            row[prec] = {"status": r.status, "iters": r.report["iters"], "time_to_tol_s": round(dt, 4),
+                         "dual_iters_per_s": round(r.report["iters"] / dt, 1), "kkt": r.report["kkt"],
+                         "y_err_bound": r.report["y_err_bound"]}
+        row["mixed_vs_fp64_y_maxabs"] = float((res["mixed_fp32"][0].y - y64).abs().max())
+        log(f"config {name}: fp64 {row['fp64']['iters']} iters {row['fp64']['time_to_tol_s']} s, "
+            f"mixed {row['mixed_fp32']['iters']} iters {row['mixed_fp32']['time_to_tol_s']} s")
+        rows.append(row)
+    return rows
 
 
 def main() -> int:
@@ -245,8 +281,10 @@ def main() -> int:
     ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
     ap.add_argument("--continuation", type=int, default=6, metavar="T",
                     help="also run T outer steps of the continuation to the unregularized estimator (0: skip)")
-    ap.add_argument("--large", type=int, default=300, metavar="K",
-                    help="also run K iterations of the N=40000, n=20 fit and report its pass rate (0: skip)")
+    ap.add_argument("--large", type=int, default=20000, metavar="K",
+                    help="also fit the N=40000, n=20 workload to tol, at most K iterations (0: skip)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the N=200 and N=2000 configurations (FP64 and mixed, to tolerance)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -399,8 +437,10 @@ def main() -> int:
         out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision, rule, restart)
     if args.continuation > 0:
         out["continuation"] = run_continuation(cr, W, args.continuation, args.precision)
+    if not args.no_configs:
+        out["configs"] = run_configs(cr, W, torch, rule, restart)
     if args.large > 0:
-        out["large_fit"] = run_large(cr, W, args.large, args.precision, rule, restart)
+        out["large_fit"] = run_large(cr, W, args.large, args.tol, args.precision, rule, restart)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations at N={wl.N} ...")
         out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters, rule, restart)
