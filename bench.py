@@ -4,8 +4,9 @@
 One step = one complete fit of the N=8000, n=40 quadratic-form workload to KKT residual 1e-4:
 Lipschitz preprocessing, P-APG iterations with the adaptive step of Section 2.4 (one fused trial
 pass each, two candidate steps per pass; a rejected pair costs another pass) and a gradient
-momentum restart (not part of the paper; ``--no-restart`` gives the paper's schedule), stopping
-tests every 50 iterations, FP64 recovery of (y, xi) and the feasible-repair certificate.
+momentum restart (not part of the paper; ``--no-restart`` gives the paper's schedule), FP64
+stopping tests (at most every 50 iterations, the next one aimed at the predicted crossing of the
+tolerance), FP64 recovery of (y, xi) and the feasible-repair certificate.
 ``--step-rule constant`` runs the constant-step variant (step 1/L, one fused pass per iteration).  Inputs are resident in
 device memory before the timed region; outputs stay on the device.
 
@@ -13,7 +14,9 @@ Prints one JSON line (stdout).  `value` is dual iterations per second over the t
 (whole-fit wall time, preprocessing and stopping tests included); `ms_per_step` is the
 time-to-tolerance of one fit.  Extra fields compare the mixed-precision path with the plain
 FP64 path on the same input, report the roofline of the fused pass, and time the FP64 CPU
-oracle on the host cores on a bounded sample of the same fit.
+oracle on the host cores on a bounded sample of the same fit.  After the timed fits the default run
+also reports the serving stream (512 requests: p50/p99 latency, fits/s), the continuation, the
+N=200 and N=2000 configurations and the N=40000 fit to tolerance.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed_fp32|mixed_bf16|fp64]
                        [--step-rule adaptive|constant] [--no-restart] [--constant-compare] [--literal-compare]
@@ -276,8 +279,9 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--max-iters", type=int, default=0,
                     help="cap the iterations of each fit (short profiling runs of the same kernels)")
-    ap.add_argument("--serving", type=int, default=0, metavar="K",
-                    help="also replay K requests of the serving stream (Poisson, 50/s) and report latency")
+    ap.add_argument("--serving", type=int, default=512, metavar="K",
+                    help="also replay K requests of the serving stream (Poisson, 50/s) and report p50/p99 "
+                         "latency and fits/s (0: skip)")
     ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
     ap.add_argument("--continuation", type=int, default=6, metavar="T",
                     help="also run T outer steps of the continuation to the unregularized estimator (0: skip)")
