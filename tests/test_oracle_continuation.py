@@ -79,3 +79,40 @@ def test_certificate_is_tight_at_the_optimum():
         ex = oracle.exact_solve(x, ybar, g)
         c = oracle.repair_certificate(x, ybar, g, ex["lam"])
         assert 0.0 <= c["cert_gap"] + 1e-14 and c["cert_gap"] <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_one_dimensional_estimator_matches_the_hinge_basis(seed):
+    """In one dimension a convex function sampled at sorted points is a + b x + sum_k c_k (x - x_k)_+
+    with c_k >= 0 (a textbook characterization: its slopes are non-decreasing), so the LS convex
+    regression is a bound-constrained least-squares problem in (a, b, c) — a formulation that
+    shares nothing with the pair constraints of eq. ``original``.  Both exact solvers and the
+    regularized P-APG fit must agree with it, and the fitted values must be convex."""
+    from scipy.optimize import lsq_linear
+    rng = np.random.default_rng(seed)
+    N = 14
+    x = np.sort(rng.uniform(-1.0, 1.0, N))
+    ybar = x ** 2 + 0.3 * np.sin(5.0 * x) + 0.05 * rng.standard_normal(N)
+    knots = x[1:-1]
+    B = np.column_stack([np.ones(N), x] + [np.maximum(0.0, x - t) for t in knots])
+    lo = np.concatenate([[-np.inf, -np.inf], np.zeros(N - 2)])
+    fit = lsq_linear(B, ybar, bounds=(lo, np.full(N, np.inf)), tol=1e-14, lsmr_tol="auto", max_iter=10000)
+    y_hinge = B @ fit.x
+    # convexity of the reference: non-negative second divided differences
+    slopes = np.diff(y_hinge) / np.diff(x)
+    assert np.all(np.diff(slopes) >= -1e-9)
+    assert np.max(np.abs(y_hinge - ybar)) > 1e-3          # the data are not convex: a real projection
+    ex = oracle.exact_ls(x[:, None], ybar)
+    # the y solve must converge; the least-norm subgradient solve may stop at a flat line search,
+    # and any feasible subgradients are at least as long as the least-norm ones (a looser bound)
+    assert ex["message"][0] == "Optimization terminated successfully"
+    assert ex["min_constraint"] >= -1e-10
+    assert np.max(np.abs(ex["y"] - y_hinge)) <= 1e-6
+    # the regularized estimator is within ||xi*|| sqrt(gamma) of y* (Section 2.4.1 with delta = 0)
+    gamma = 1e-6
+    r = oracle.papg(x[:, None], ybar, gamma, 1e-10, adaptive=True, restart=True, max_iters=200000)
+    gap = oracle.repair_certificate(x[:, None], ybar, gamma, r["lam"])["cert_gap"]
+    bound = np.linalg.norm(ex["xi"]) * math.sqrt(gamma) + math.sqrt(2.0 * gap)
+    assert np.linalg.norm(r["y"] - y_hinge) <= bound + 1e-9
+    s_fit = np.diff(r["y"]) / np.diff(x)
+    assert np.all(np.diff(s_fit) >= -1e-4)
