@@ -66,3 +66,46 @@ def test_set_delta_warm_start_matches_oracle(cr, torch_dev):
     # certified: ||y - y*_gamma|| <= sqrt(2 G)
     assert np.linalg.norm(y - ex["y"]) <= math.sqrt(2 * rep2["cert_gap"]) + 1e-9
     assert rep2["L"] == pytest.approx(rep1["L"] * g1 / g2, rel=1e-12)
+
+
+def _hinge_estimator(x, ybar):
+    """The 1-D LS convex regression as bounded least squares over a + b x + sum_k c_k (x - x_k)_+,
+    c >= 0 (sorted x), with the least-norm subgradients of the fitted function at every point."""
+    from scipy.optimize import lsq_linear
+    order = np.argsort(x)
+    xs, ys = x[order], ybar[order]
+    N = xs.size
+    B = np.column_stack([np.ones(N), xs] + [np.maximum(0.0, xs - t) for t in xs[1:-1]])
+    lo = np.concatenate([[-np.inf, -np.inf], np.zeros(N - 2)])
+    fit = lsq_linear(B, ys, bounds=(lo, np.full(N, np.inf)), tol=1e-14, lsmr_tol="auto", max_iter=20000)
+    yh = B @ fit.x
+    s = np.diff(yh) / np.diff(xs)
+    left = np.concatenate([[-np.inf], s])       # subgradient interval [left, right] at each point
+    right = np.concatenate([s, [np.inf]])
+    xi = np.clip(0.0, left, right)
+    y = np.empty(N)
+    y[order] = yh
+    xi_full = np.empty(N)
+    xi_full[order] = xi
+    return y, xi_full
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_continuation_one_dimensional_matches_hinge_basis(cr, torch_dev, precision):
+    """At N = 200 (far beyond the dense exact solvers) the one-dimensional estimator has a closed
+    characterization: bounded least squares in the hinge basis.  The continuation's last iterate
+    must lie within the section's bound ||xi*|| sqrt(gamma_T) + sqrt(2 delta_T) of it."""
+    rng = np.random.default_rng(21)
+    N = 200
+    x1 = rng.uniform(-1.0, 1.0, N)
+    ybar = x1 ** 2 + 0.2 * np.sin(4.0 * x1) + 0.1 * rng.standard_normal(N)
+    y_star, xi_star = _hinge_estimator(x1, ybar)
+    T = 10
+    r = cr.fit_continuation(x1[:, None], ybar, 1.0, 2.0, 1.0, 1.0, T, cr.Options(precision=precision),
+                            allow_noconv=False)
+    last = r.extra["steps"][-1]
+    assert last["status"] == cr.CR_OK and 0.0 <= last["cert_gap"] <= last["delta"]
+    bound = np.linalg.norm(xi_star) * math.sqrt(last["gamma"]) + math.sqrt(2 * last["delta"])
+    assert np.linalg.norm(r.y - y_star) <= bound
+    # a real projection: the data are far from convex, the fit is close to the estimator
+    assert np.linalg.norm(r.y - y_star) < 0.5 * np.linalg.norm(ybar - y_star)
