@@ -304,6 +304,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    from paper_1608_02227_amd import build as crbuild
+    if not os.path.exists(crbuild.LIB):   # a tree that was never built: build it (loading is strict)
+        crbuild.build(verbose=True)
     cr.load()
     dev = torch.device("cuda:0")
     wl = W.WORKLOADS[WORKLOAD]

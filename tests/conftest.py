@@ -23,7 +23,11 @@ def gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def cr():
-    """The C-ABI binding; fails loudly when the library is missing."""
+    """The C-ABI binding.  A tree without a built library builds it first (hipcc cross-compiles for
+    gfx950 without a GPU); loading then fails loudly if the build did not produce it."""
+    from paper_1608_02227_amd import build as _build
     from paper_1608_02227_amd import cr as _cr
+    if not os.path.exists(_build.LIB):
+        _build.build()
     _cr.load()
     return _cr
