@@ -258,6 +258,13 @@ def test_dual_value_closed_form_and_gap_identity():
     s = oracle.pair_residual(x, y, xi)
     gap = oracle.primal_objective(ybar, gamma, y, xi) - g
     assert gap == pytest.approx(np.sum(lam * s), rel=1e-10)
+    # the stopping report's complementarity sum and dual value, against the explicit constraint
+    # matrices (constraint values A1 y + A2 xi in the pair order of Definition def:A1A2)
+    cvals = A1 @ y + A2 @ xi.reshape(-1)
+    assert cvals.min() < 0.0 < cvals.max()                  # violated pairs carry multipliers too
+    rep = oracle.kkt_report(x, ybar, gamma, lam)
+    assert rep["comp_sum"] == pytest.approx(float(theta @ cvals), rel=1e-10)
+    assert rep["dual_obj"] == pytest.approx(g_cf, rel=1e-10)
 
 
 def test_dual_gradient_finite_difference():
