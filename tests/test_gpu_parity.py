@@ -359,3 +359,48 @@ def test_deterministic_repeat(cr, torch_dev):
     b = cr.fit(x, ybar, 1e-3, 1e-12, opt, return_lambda=True)
     np.testing.assert_array_equal(a.lam, b.lam)
     np.testing.assert_array_equal(a.y, b.y)
+
+
+# Feature widths at the edges of the 16-wide blocks (MB = ceil((n + 1) / 16)) and of the trimmed
+# residual K-steps (the per-iteration passes run ceil(n / 4) of the 4 MB steps when that saves two
+# or more): n = 1, 16, 32, 48 trim, n = 15, 31, 47, 63 do not; the row counts are ragged.
+WIDTHS = [(70, 1), (97, 15), (81, 16), (65, 31), (129, 32), (75, 47), (66, 48), (90, 63)]
+
+
+@pytest.mark.parametrize("N,n", WIDTHS)
+def test_feature_width_edges_match_oracle(cr, torch_dev, N, n):
+    x, ybar = W.sq_norm(N, n, 0.1, 100 + n)
+    delta = 1e-3
+    L, _, _ = oracle.lipschitz(x, delta)
+    its_c, its_a, its_p, steps = [], [], [], []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, iterates=its_c)
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, iterates=its_a, adaptive=True,
+                restart=True, steps=steps)
+    yp = ybar * (1.0 + 1e-15 * np.random.default_rng(5).standard_normal(N))
+    oracle.papg(x, yp, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, iterates=its_p, adaptive=True,
+                restart=True)
+    ref_c, ref_a, ref_p = its_c[-1][1], its_a[-1][1], its_p[-1][1]
+    # FP64, constant step: summation order only
+    with cr.Solver(x, ybar, delta, cr.Options(step_rule="constant")) as s:
+        s.set_L(L)
+        s.iterate(10)
+        lam = s.lam()
+    assert np.max(np.abs(lam - ref_c)) <= 1e-10 * np.abs(ref_c).max()
+    # FP64, adaptive step with restart: the same accepted steps, iterates within the trajectory's spread
+    with cr.Solver(x, ybar, delta, cr.Options()) as s:
+        s.set_L(L)
+        s.iterate(10)
+        lam = s.lam()
+        assert s.report()["step_final"] == steps[-1]
+    scale = np.abs(ref_a).max()
+    spread = np.max(np.abs(ref_p - ref_a)) / scale
+    assert np.max(np.abs(lam - ref_a)) <= max(1e-10, 100.0 * spread) * scale
+    # mixed FP32 (split state, FP32 MFMA residual, BF16-split adjoints in the trial passes): the
+    # mixed-precision bar of 1e-4 of the multiplier scale
+    for precision, step_rule, ref in [("mixed_fp32", "constant", ref_c), ("mixed_fp32", "adaptive", ref_a)]:
+        with cr.Solver(x, ybar, delta, cr.Options(precision=precision, step_rule=step_rule)) as s:
+            s.set_L(L)
+            s.iterate(10)
+            lam = s.lam()
+        assert np.max(np.abs(lam - ref)) <= max(1e-4, 100.0 * spread) * np.abs(ref).max(), (precision, step_rule)
+        assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
