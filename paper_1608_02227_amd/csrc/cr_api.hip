@@ -216,6 +216,12 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         return bail(CR_ENOMEM);
     std::memset(s->h_scal, 0, 32 * sizeof(double));
     if (hipEventCreate(&s->ev_a) != hipSuccess || hipEventCreate(&s->ev_b) != hipSuccess) return bail(CR_EDEVICE);
+    // a state larger than the free device memory is refused before any O(N^2) allocation
+    {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && cr_state_bytes(N, n, opt.precision, s->adaptive) > fr)
+            return bail(CR_ENOMEM);
+    }
 
     const Geometry &g = s->g;
     const size_t nr = g.Nr, np = g.NP, rows_np = nr * np;

@@ -190,6 +190,54 @@ def test_large_fit_N40000(cr, torch_dev):
     assert rep["kkt"] < 1.0
 
 
+def test_pair_indices_beyond_2_31(cr, torch_dev):
+    """N = 50000 pads to 50,048 rows and columns: 2.5e9 stored pairs, so from row 42,909 on the
+    offset of a pair in the multiplier arrays exceeds 2^31 and every kernel must index in 64 bits.
+    The first constant step from lam = 0 has the closed form lam_rj = (-(ybar_j - ybar_r)/L)_+
+    (eta(0) = (ybar, 0)); rows on both sides of the boundary and the last rows are checked in both
+    stored forms, then adaptive steps run and the report keeps its identities."""
+    N, delta = 50000, 1e-3
+    x, ybar = W.make("maxaff16_N40000_n20", seed=3, N=N)
+    rows = [0, 1, 21454, 42908, 42909, 42910, 49998, 49999]
+    for precision, tol in [("mixed_fp32", 1e-6), ("fp64", 1e-12)]:
+        with cr.Solver(x, ybar, delta, cr.Options(precision=precision, step_rule="constant")) as s:
+            L, _, _ = s.lipschitz()
+            s.iterate(1)
+            for r in rows:
+                got = s.lam_rows(r, 1)[0]
+                ref = np.maximum(0.0, -(ybar - ybar[r]) / L)
+                ref[r] = 0.0
+                assert np.max(np.abs(got - ref)) <= tol * max(1e-300, np.abs(ref).max()), (precision, r)
+    with cr.Solver(x, ybar, delta, cr.Options(precision="mixed_fp32")) as s:
+        L, _, _ = s.lipschitz()
+        s.iterate(20)
+        for r in rows[3:]:
+            got = s.lam_rows(r, 1)[0]
+            assert np.all(np.isfinite(got)) and np.all(got >= 0.0) and got[r] == 0.0
+        rep = s.report()
+    assert rep["iters"] == 20
+    assert rep["dual_obj"] > 0.0 and rep["cert_gap"] >= 0.0
+    assert rep["dual_obj"] == pytest.approx(rep["primal_obj"] - rep["comp_sum"], rel=1e-12)
+    e = math.log2(rep["step_final"] / L)
+    assert e == round(e)
+
+
+def test_state_beyond_device_memory_is_refused(cr, torch_dev):
+    """N = 190,000 in mixed FP32 needs three 145 GB multiplier arrays, more than one device holds:
+    the fit is refused with CR_ENOMEM before it allocates them, and the device still runs a small
+    fit afterwards."""
+    N = 190000
+    g = np.random.default_rng(0)
+    x = g.uniform(-1.0, 1.0, size=(N, 2))
+    ybar = (x ** 2).sum(axis=1)
+    with pytest.raises(cr.CRError) as e:
+        cr.fit(x, ybar, 1e-3, 1e-4, cr.Options(precision="mixed_fp32"))
+    assert e.value.code == cr.CR_ENOMEM
+    xs, ys = W.sq_norm(200, 2, 0.1, 0)
+    r = cr.fit(xs, ys, 1e-3, 1e-4, cr.Options(precision="mixed_fp32"), allow_noconv=False)
+    assert r.report["kkt"] <= 1e-4
+
+
 @pytest.mark.parametrize("rule", ["constant", "adaptive"])
 def test_step_parity_lse8_N2000(cr, torch_dev, rule):
     """The N=2000, n=10 configuration (FP64): one step of the oracle from the GPU's iterates."""
