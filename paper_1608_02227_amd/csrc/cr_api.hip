@@ -264,6 +264,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
         CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
         CR_ALLOC(s->block_part, (size_t)(g.Nr / 16) * 4 * 8);
+        CR_ALLOC(s->decision, 4 * 8);
         for (int q = 0; q < 2; ++q) {
             CR_ALLOC(s->uD[q], nr * 8);
             CR_ALLOC(s->wD[q], rows_np * 8);
@@ -516,6 +517,7 @@ int cr_solver::step_adaptive() {
     int accepted = -1;
     double s_new = s_step;
     bool restart_now = false;
+    double beta_dev = 0.0, t_next_dev = 1.0;
     const bool defer = deferred();
     for (int attempt = 0; attempt < 64; ++attempt) {
         // split forms: the first attempt also re-forms and stores the previous accepted iterate
@@ -571,10 +573,26 @@ int cr_solver::step_adaptive() {
         f.wD[0] = wD[0]; f.wD[1] = wD[1];
         f.block_part = block_part;
         // h_scal (pinned host memory) receives ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b,
-        // ||D_a||^2, ||D_b||^2, <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>
+        // ||D_a||^2, ||D_b||^2, <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>, then the decision
+        // (candidate or -1 / -2, beta_k, t_{k+1}, restart)
         CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
         const unsigned long long seq = ++trial_seq;
-        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_scal, h_seq(), seq, stream));
+        // the reduction takes the step test's decision on the device (the same FP64 operations
+        // as written here before), and the accepted step's update is queued right behind it: it
+        // reads that decision and does nothing on a retry, so no host round trip sits between
+        // the test and the update.  Its outputs go to the pass-array set that becomes current on
+        // acceptance (split forms keep this trial's set for re-forming the candidate).
+        const TrialRule rule{sa, sb, delta, t, opt.restart ? 1 : 0, opt.momentum ? 1 : 0};
+        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_scal, h_seq(), seq, rule, decision, stream));
+        {
+            const int en = 1 - ecur;
+            double *yn = defer ? yo64 : y64, *xin = defer ? xio64 : xi64, *dmyn = defer ? dmyo64 : dmy64;
+            float *y32n = fp32pass ? (defer ? yo32 : y32) : nullptr;
+            float *xi32n = fp32pass ? (defer ? xio32 : xi32) : nullptr;
+            float *dmy32n = fp32pass ? (defer ? dmyo32 : dmy32) : nullptr;
+            CR_HIP(launch_accept(g, y64, xi64, yn, xin, dmyn, uD, wD, ye[ecur], xie[ecur], ye[en], xie[en], dmye[en],
+                                 y32n, xi32n, dmy32n, xhat64, 1.0 / delta, 0.0, decision, stream));
+        }
         {
             const int rc = wait_trial(seq);
             if (rc) return rc;
@@ -583,9 +601,16 @@ int cr_solver::step_adaptive() {
         trials += 2.0;
         for (int q = 0; q < 8; ++q)
             if (!std::isfinite(h_scal[q])) return CR_ENUMERIC;
-        const double curv_a = h_scal[0] + h_scal[1] / delta, curv_b = h_scal[2] + h_scal[3] / delta;
-        if (curv_a <= sa * h_scal[4] * (1.0 + 1e-12)) { accepted = 0; s_new = sa; restart_now = h_scal[6] < 0.0; break; }
-        if (curv_b <= sb * h_scal[5] * (1.0 + 1e-12)) { accepted = 1; s_new = sb; restart_now = h_scal[7] < 0.0; break; }
+        const double acc = h_scal[8];
+        if (acc < -1.5) return CR_ENUMERIC;
+        if (acc >= 0.0) {
+            accepted = acc > 0.5 ? 1 : 0;
+            s_new = accepted ? sb : sa;
+            restart_now = h_scal[11] != 0.0;
+            beta_dev = h_scal[9];
+            t_next_dev = h_scal[10];
+            break;
+        }
         sa = sb * upsilon;
         sb = sa * upsilon;
     }
@@ -601,27 +626,19 @@ int cr_solver::step_adaptive() {
         else { cur = B; prv = c; fa = A; fb = p; }
     }
     // optional gradient restart: the accepted step points against the iterate's own movement
-    if (opt.restart && restart_now) {
-        t = 1.0;
-        restarts += 1.0;
-    }
-    const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
-    // eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta) into the slot of eta(lam^{k-1}),
-    // and the pass arrays (1 + beta_k) eta(lam^{k+1}) - beta_k eta(lam^k) for the next iteration
+    // (decided on the device: t_{k+1} and beta_k there already start again from t = 1)
+    if (restart_now) restarts += 1.0;
+    // the queued update has written eta(lam^{k+1}) = eta(lam~^{k+1}) + (A1^T D, A2^T D / delta)
+    // into the slot of eta(lam^{k-1}) and the pass arrays (1 + beta_k) eta(lam^{k+1}) -
+    // beta_k eta(lam^k) into the other set, which becomes the current one
     const int en = 1 - ecur;
     if (defer) {
-        // keep this trial's pass arrays for re-forming its candidate; the next ones go to the others
         std::swap(y64, yo64); std::swap(xi64, xio64); std::swap(dmy64, dmyo64);
         std::swap(y32, yo32); std::swap(xi32, xio32); std::swap(dmy32, dmyo32);
     }
-    const double *yt = defer ? yo64 : y64, *xit = defer ? xio64 : xi64;
-    CR_HIP(launch_accept(g, yt, xit, y64, xi64, dmy64, uD[accepted], wD[accepted], ye[ecur], xie[ecur], ye[en],
-                         xie[en], dmye[en], fp32pass ? y32 : nullptr, fp32pass ? xi32 : nullptr,
-                         fp32pass ? dmy32 : nullptr, xhat64, 1.0 / delta, beta_k, stream));
     ecur = en;
-    t = t_next;
-    beta_last = beta_k;
+    t = t_next_dev;
+    beta_last = beta_dev;
     s_step = s_new;
     ++k;
     if (fp32pass) ++k_low;

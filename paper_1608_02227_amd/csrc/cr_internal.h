@@ -46,6 +46,7 @@ struct cr_solver {
     // FP64 primal points eta(lam^k) (index ecur) and eta(lam^{k-1}) (index 1 - ecur)
     void *part_acc2 = nullptr, *part_col2 = nullptr;
     double *block_part = nullptr;   // per-block sums of the trial finalize
+    double *decision = nullptr;     // the trial reduction's step decision (device, 4 values)
     unsigned timing_tick = 0;       // samples one in four trial launches for the pass timing
     double *uD[2] = {nullptr, nullptr}, *wD[2] = {nullptr, nullptr};
     double *ye[2] = {nullptr, nullptr}, *xie[2] = {nullptr, nullptr}, *dmye[2] = {nullptr, nullptr};

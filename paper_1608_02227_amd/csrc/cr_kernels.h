@@ -158,20 +158,33 @@ struct TrialFinalizeArgs {
 };
 hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st);
 
+// What the trial reduction needs to take the step test's decision itself: the two candidates'
+// s values, delta, the current t_k, and the restart and momentum options.
+struct TrialRule {
+    double s_a, s_b, delta, t;
+    int restart, momentum;
+};
+
 // The eight trial scalars: out[0..3] = column sums of block_part ((Nr / 16) x 4), out[4..7] = sums
-// of part_red slots 0..3 over the pass's workgroups.  Single workgroup, fixed order; `out` may be
-// pinned host memory.  If seq_out is set, `seq` is written there after the eight values are
-// visible at system scope (a host polling pinned memory may then read them).
+// of part_red slots 0..3 over the pass's workgroups; then the step test's decision in out[8..11]
+// and, if `decision` is set, in device memory there too (candidate 0 / 1, -1 for neither, -2 for
+// a non-finite scalar; beta_k; t_{k+1}; restart flag).  Single workgroup, fixed order; `out` may be
+// pinned host memory.  If seq_out is set, `seq` is written there after the values are visible at
+// system scope (a host polling pinned memory may then read them).
 hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,
-                               unsigned long long *seq_out, unsigned long long seq, hipStream_t st);
+                               unsigned long long *seq_out, unsigned long long seq, const TrialRule &rule,
+                               double *decision, hipStream_t st);
 
 
 // Accepted adaptive step: eta(lam^{k+1}) from eta(lam~^{k+1}) (yt, xit) and the adjoint of D,
-// then the next pass arrays (1 + beta) eta(lam^{k+1}) - beta eta(lam^k) into (y, xi, dmy).
+// then the next pass arrays (1 + beta) eta(lam^{k+1}) - beta eta(lam^k) into (y, xi, dmy).  With
+// `decision` (the trial reduction's device output) the candidate and beta are taken from there and
+// the launch does nothing when no candidate was accepted, so it can be queued before the host has
+// seen the test; without it candidate 0 and `beta` are used.
 hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit, double *y, double *xi, double *dmy,
-                         const double *uD, const double *wD, const double *yk, const double *xik, double *ye,
-                         double *xie, double *dmye, float *y32, float *xi32, float *dmy32, const double *xhat64,
-                         double inv_delta, double beta, hipStream_t st);
+                         const double *const uD[2], const double *const wD[2], const double *yk, const double *xik,
+                         double *ye, double *xie, double *dmye, float *y32, float *xi32, float *dmy32,
+                         const double *xhat64, double inv_delta, double beta, const double *decision, hipStream_t st);
 
 // Sums / maxima of per-block partials: out[q] = op_q over blocks of part[b * stride + q],
 // with op = max for q < nmax and sum otherwise.  Single workgroup, deterministic order.

@@ -1278,12 +1278,23 @@ hipError_t launch_lincomb(const Geometry &g, const double *ya, const double *xia
 // (ye, xie, dmye), then the next extrapolated point (1 + beta) eta(lam^{k+1}) - beta eta(lam^k) into
 // the pass arrays (y, xi, dmy and their FP32 copies).  (yt, xit) hold eta(lam~^{k+1}); they may be
 // the same arrays as (y, xi).
+// With `decision` set, the candidate (0 or 1; negative: none, the kernel does nothing) and beta
+// are read from decision[0], decision[1] as the trial reduction left them, and uD / wD point at
+// the two candidates' adjoints; otherwise candidate 0 and the `beta` argument are used.
 __global__ __launch_bounds__(256) void accept_kernel(const double *yt, const double *xit, double *y, double *xi,
-                                                    double *dmy, const double *uD,
-                                                    const double *wD, const double *yk, const double *xik,
-                                                    double *ye, double *xie, double *dmye, float *y32, float *xi32,
-                                                    float *dmy32, const double *xhat64, double inv_delta, double beta,
+                                                    double *dmy, const double *uD0, const double *uD1,
+                                                    const double *wD0, const double *wD1, const double *yk,
+                                                    const double *xik, double *ye, double *xie, double *dmye,
+                                                    float *y32, float *xi32, float *dmy32, const double *xhat64,
+                                                    double inv_delta, double beta, const double *decision,
                                                     int N, int n, int NP) {
+    const double *uD = uD0, *wD = wD0;
+    if (decision) {
+        const double acc = decision[0];
+        if (acc < 0.0) return;
+        beta = decision[1];
+        if (acc > 0.5) { uD = uD1; wD = wD1; }
+    }
     const int t = threadIdx.x & 15;
     const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
     double dn = 0.0, dp = 0.0;
@@ -1317,11 +1328,12 @@ __global__ __launch_bounds__(256) void accept_kernel(const double *yt, const dou
 }
 
 hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit, double *y, double *xi, double *dmy,
-                         const double *uD, const double *wD, const double *yk, const double *xik, double *ye,
-                         double *xie, double *dmye, float *y32, float *xi32, float *dmy32, const double *xhat64,
-                         double inv_delta, double beta, hipStream_t st) {
-    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, yt, xit, y, xi, dmy, uD, wD, yk, xik, ye,
-                       xie, dmye, y32, xi32, dmy32, xhat64, inv_delta, beta, g.N, g.n, g.NP);
+                         const double *const uD[2], const double *const wD[2], const double *yk, const double *xik,
+                         double *ye, double *xie, double *dmye, float *y32, float *xi32, float *dmy32,
+                         const double *xhat64, double inv_delta, double beta, const double *decision, hipStream_t st) {
+    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, yt, xit, y, xi, dmy, uD[0], uD[1], wD[0],
+                       wD[1], yk, xik, ye, xie, dmye, y32, xi32, dmy32, xhat64, inv_delta, beta, decision, g.N, g.n,
+                       g.NP);
     return hipGetLastError();
 }
 
@@ -1400,9 +1412,17 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
 // The eight trial scalars in one single-workgroup launch, fixed order: out[q] = sum_b pa[b * 4 + q]
 // for q < 4 (the finalize's per-block sums), out[4 + q] = sum_b pb[b * kRed + q] (the pass's
 // reduction slots).  `out` may be pinned host memory (written once, read after the stream syncs).
+//
+// It also takes the step test's decision (eq. "eq:adaptive-check" with every pair dualized:
+// ||A1^T D||^2 + ||A2^T D||^2 / delta <= s ||D||^2, candidate a first), so that the accept kernel
+// queued behind it needs no host round trip: decision[0] = 0 / 1 (candidate), -1 (neither: retry),
+// -2 (a non-finite scalar); decision[1] = beta_k, decision[2] = t_{k+1}, decision[3] = 1 if the
+// momentum restarts (restart on and <D, candidate - lam^k> < 0).  The same four values follow the
+// eight scalars in out[8..11].
 __global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int ba, const double *pb, int bb,
                                                           double *out, unsigned long long *seq_out,
-                                                          unsigned long long seq) {
+                                                          unsigned long long seq, TrialRule rule,
+                                                          double *decision) {
     __shared__ double sh[8][256];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1424,6 +1444,25 @@ __global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) out[q] = sh[q][0];
+        double acc = -1.0, rs = 0.0, tt = rule.t;
+        bool finite = true;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) finite = finite && isfinite(sh[q][0]);
+        if (!finite) {
+            acc = -2.0;
+        } else {
+            const double curv_a = sh[0][0] + sh[1][0] / rule.delta, curv_b = sh[2][0] + sh[3][0] / rule.delta;
+            if (curv_a <= rule.s_a * sh[4][0] * (1.0 + 1e-12)) { acc = 0.0; rs = sh[6][0] < 0.0 ? 1.0 : 0.0; }
+            else if (curv_b <= rule.s_b * sh[5][0] * (1.0 + 1e-12)) { acc = 1.0; rs = sh[7][0] < 0.0 ? 1.0 : 0.0; }
+        }
+        if (!rule.restart) rs = 0.0;
+        if (rs != 0.0) tt = 1.0;
+        const double t_next = (1.0 + sqrt(1.0 + 4.0 * tt * tt)) / 2.0;
+        const double beta_k = rule.momentum ? (tt - 1.0) / t_next : 0.0;
+        out[8] = acc; out[9] = beta_k; out[10] = t_next; out[11] = rs;
+        if (decision) {
+            decision[0] = acc; decision[1] = beta_k; decision[2] = t_next; decision[3] = rs;
+        }
         if (seq_out) {
             // the eight values reach system scope before the sequence word that announces them
             __threadfence_system();
@@ -1433,9 +1472,10 @@ __global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int
 }
 
 hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,
-                               unsigned long long *seq_out, unsigned long long seq, hipStream_t st) {
+                               unsigned long long *seq_out, unsigned long long seq, const TrialRule &rule,
+                               double *decision, hipStream_t st) {
     hipLaunchKernelGGL(trial_reduce_kernel, dim3(1), dim3(256), 0, st, block_part, g.Nr / 16, part_red, g.grid(),
-                       out, seq_out, seq);
+                       out, seq_out, seq, rule, decision);
     return hipGetLastError();
 }
 
