@@ -404,3 +404,32 @@ def test_feature_width_edges_match_oracle(cr, torch_dev, N, n):
             lam = s.lam()
         assert np.max(np.abs(lam - ref)) <= max(1e-4, 100.0 * spread) * np.abs(ref).max(), (precision, step_rule)
         assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
+
+
+@pytest.mark.parametrize("step_rule", ["constant", "adaptive"])
+def test_promotion_mid_fit_matches_oracle(cr, torch_dev, step_rule):
+    """The FP64 promotion a stalled mixed fit falls back on, taken after 5 mixed-FP32 steps: the
+    multipliers carry over exactly (H + l merged in FP64, the pending adaptive iterate stored first),
+    the step state (t, beta, s_k) carries on, and the next 5 FP64 steps keep the trajectory on the
+    oracle's to the mixed-precision bar."""
+    x, ybar = W.make("lse8_N2000_n10", seed=1, N=150)
+    delta = 1e-3
+    L, _, _ = oracle.lipschitz(x, delta)
+    adaptive = step_rule == "adaptive"
+    its = []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, iterates=its, adaptive=adaptive,
+                restart=True)
+    ref = dict(its)
+    with cr.Solver(x, ybar, delta, cr.Options(precision="mixed_fp32", step_rule=step_rule)) as s:
+        s.set_L(L)
+        s.iterate(5)
+        lam5 = s.lam()
+        s.promote()
+        np.testing.assert_array_equal(s.lam(), lam5)
+        assert np.max(np.abs(lam5 - ref[5])) <= 1e-4 * np.abs(ref[5]).max()
+        s.iterate(5)
+        lam = s.lam()
+        rep = s.report()
+    assert rep["iters"] == 10 and rep["iters_low"] == 5
+    assert np.max(np.abs(lam - ref[10])) <= 1e-4 * np.abs(ref[10]).max()
+    assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
