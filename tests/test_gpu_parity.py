@@ -433,3 +433,43 @@ def test_promotion_mid_fit_matches_oracle(cr, torch_dev, step_rule):
     assert rep["iters"] == 10 and rep["iters_low"] == 5
     assert np.max(np.abs(lam - ref[10])) <= 1e-4 * np.abs(ref[10]).max()
     assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
+
+
+@pytest.mark.parametrize("precision,step_rule,bar", [("fp64", "constant", 1e-10), ("fp64", "adaptive", None),
+                                                     ("mixed_fp32", "constant", 1e-4), ("mixed_fp32", "adaptive", 1e-4)])
+def test_start_from_given_multipliers_matches_oracle(cr, torch_dev, precision, step_rule, bar):
+    """A solver created from lambda0 (the oracle's lam^5 of another run, diagonal nonzero on purpose)
+    holds it exactly (FP64) or to FP32-split rounding (mixed), with the diagonal dropped, and its
+    next 10 steps (t restarting at 1, as for theta^0 in the paper's method) follow the oracle's run
+    from the same lam^0.  The FP64 adaptive bar is the oracle's own spread (see the adaptive test)."""
+    x, ybar = W.make("lse8_N2000_n10", seed=2, N=140)
+    delta = 1e-3
+    L, _, _ = oracle.lipschitz(x, delta)
+    pre = []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=5, check_every=10 ** 9, iterates=pre)
+    lam0 = pre[-1][1].copy()
+    np.fill_diagonal(lam0, 0.25)
+    adaptive = step_rule == "adaptive"
+    its, its_p = [], []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, lam0=lam0, iterates=its,
+                adaptive=adaptive, restart=True)
+    yp = ybar * (1.0 + 1e-15 * np.random.default_rng(3).standard_normal(len(ybar)))
+    oracle.papg(x, yp, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, lam0=lam0, iterates=its_p,
+                adaptive=adaptive, restart=True)
+    ref, refp = its[-1][1], its_p[-1][1]
+    want0 = lam0.copy()
+    np.fill_diagonal(want0, 0.0)
+    with cr.Solver(x, ybar, delta, cr.Options(precision=precision, step_rule=step_rule), lambda0=lam0) as s:
+        got0 = s.lam()
+        if precision == "fp64":
+            np.testing.assert_array_equal(got0, want0)
+        else:
+            assert np.max(np.abs(got0 - want0)) <= 1e-13 * np.abs(want0).max()
+        s.set_L(L)
+        s.iterate(10)
+        lam = s.lam()
+    scale = np.abs(ref).max()
+    if bar is None:
+        bar = max(1e-10, 100.0 * np.max(np.abs(refp - ref)) / scale)
+    assert np.max(np.abs(lam - ref)) <= bar * scale
+    assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
