@@ -473,3 +473,21 @@ def test_start_from_given_multipliers_matches_oracle(cr, torch_dev, precision, s
         bar = max(1e-10, 100.0 * np.max(np.abs(refp - ref)) / scale)
     assert np.max(np.abs(lam - ref)) <= bar * scale
     assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
+
+
+def test_time_budget_and_zero_iteration_cap(cr, torch_dev):
+    """The wall-clock budget is checked after each stopping test, so a fit that cannot reach tol
+    returns CR_ENOCONV within one test interval of the budget, with a finite report and a valid
+    certificate; max_iters = 0 returns the zero start's report without iterating."""
+    x, ybar = W.make("lse8_N2000_n10", seed=0, N=1200)
+    opt = cr.Options(step_rule="constant", time_budget_s=0.05, check_every=50, checks="fixed")
+    r = cr.fit(x, ybar, 1e-3, 1e-9, opt)
+    assert r.status == cr.CR_ENOCONV
+    assert r.report["iters"] > 0 and r.report["iters"] % 50 == 0
+    assert r.report["seconds"] < 0.05 + 2.0
+    assert math.isfinite(r.report["kkt"]) and r.report["cert_gap"] >= 0.0
+    r0 = cr.fit(x, ybar, 1e-3, 1e-9, cr.Options(max_iters=0))
+    assert r0.status == cr.CR_ENOCONV and r0.report["iters"] == 0
+    # at lam = 0 the fitted values are the observations and the slopes vanish
+    np.testing.assert_array_equal(r0.y, ybar)
+    assert np.all(r0.xi == 0.0)
