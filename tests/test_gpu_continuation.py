@@ -24,7 +24,8 @@ def torch_dev():
     return torch
 
 
-@pytest.mark.parametrize("precision,seed,kind", [("fp64", 5, "sq"), ("fp64", 7, "lse"), ("mixed_fp32", 6, "sq")])
+@pytest.mark.parametrize("precision,seed,kind", [("fp64", 5, "sq"), ("fp64", 7, "lse"), ("mixed_fp32", 6, "sq"),
+                                                  ("mixed_bf16", 8, "lse")])
 def test_continuation_matches_oracle_and_bound(cr, torch_dev, precision, seed, kind):
     if kind == "sq":
         x, ybar = W.sq_norm(12, 2, 0.1, seed)
@@ -90,7 +91,7 @@ def _hinge_estimator(x, ybar):
     return y, xi_full
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32", "mixed_bf16"])
 def test_continuation_one_dimensional_matches_hinge_basis(cr, torch_dev, precision):
     """At N = 200 (far beyond the dense exact solvers) the one-dimensional estimator has a closed
     characterization: bounded least squares in the hinge basis.  The continuation's last iterate

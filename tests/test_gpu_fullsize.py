@@ -55,7 +55,7 @@ def _oracle_step(x, ybar, delta, L, lam_km1, lam_km2, k):
     return lam
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed_fp32", 1e-5)])
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed_fp32", 1e-5), ("mixed_bf16", 1e-5)])
 def test_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
     x, ybar = quad8000
     delta = 1e-3
@@ -96,7 +96,7 @@ def _oracle_adaptive_step(x, ybar, delta, s_prev, lam_km1, lam_km2, k, upsilon=2
         ell += 1
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed_fp32", 1e-5)])
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed_fp32", 1e-5), ("mixed_bf16", 1e-5)])
 def test_adaptive_step_parity_N8000(cr, torch_dev, quad8000, precision, rtol):
     x, ybar = quad8000
     delta = 1e-3

@@ -32,7 +32,7 @@ def _requests(count, seed):
     return out
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16", "fp64"])
 def test_mix_equals_alone(cr, torch_dev, precision):
     reqs = _requests(8, 3)
     opt = cr.Options(precision=precision, max_iters=3000)
