@@ -577,9 +577,10 @@ int cr_solver::step_adaptive() {
         // (candidate or -1 / -2, beta_k, t_{k+1}, restart)
         CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
         const unsigned long long seq = ++trial_seq;
-        // the reduction takes the step test's decision on the device (the same FP64 operations
-        // as written here before), and the accepted step's update is queued right behind it: it
-        // reads that decision and does nothing on a retry, so no host round trip sits between
+        // the reduction takes the step test's decision on the device (both candidates, the
+        // restart, t_{k+1} and beta_k, in FP64; the host reads that decision back rather than
+        // evaluating the test again), and the accepted step's update is queued right behind it:
+        // it reads the decision and does nothing on a retry, so no host round trip sits between
         // the test and the update.  Its outputs go to the pass-array set that becomes current on
         // acceptance (split forms keep this trial's set for re-forming the candidate).
         const TrialRule rule{sa, sb, delta, t, opt.restart ? 1 : 0, opt.momentum ? 1 : 0};
