@@ -13,7 +13,8 @@ device memory before the timed region; outputs stay on the device.
 Prints one JSON line (stdout).  `value` is dual iterations per second over the timed fits
 (whole-fit wall time, preprocessing and stopping tests included); `ms_per_step` is the
 time-to-tolerance of one fit.  Extra fields compare the mixed-precision path with the plain
-FP64 path on the same input, report the roofline of the fused pass, and time the FP64 CPU
+FP64 path and with the BF16-high-part split form on the same input (context, not `value`),
+report the roofline of the fused pass, and time the FP64 CPU
 oracle on the host cores on a bounded sample of the same fit.  After the timed fits the default run
 also reports the serving stream (512 requests: p50/p99 latency, fits/s), the continuation, the
 N=200 and N=2000 configurations and the N=40000 fit to tolerance.
@@ -397,6 +398,23 @@ def main() -> int:
             "mixed_vs_fp64_y_rel": float(np.max(np.abs(ymix - y64)) / np.max(np.abs(y64))),
         })
         log(f"fp64 comparison: {rep64['iters']} iters in {dt64:.2f} s")
+        if args.precision == "mixed_fp32":
+            # the other split form (BF16 high part, 14 instead of 16 bytes per pair in the hot pass):
+            # context only, never `value`; warmed once, then timed once
+            one_fit("mixed_bf16")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rbf = one_fit("mixed_bf16")
+            torch.cuda.synchronize()
+            dtb = time.perf_counter() - t1
+            ybf = rbf.y.cpu().numpy()
+            extra.update({
+                "mixed_bf16_time_to_tol_s": round(dtb, 4),
+                "mixed_bf16_iters": rbf.report["iters"],
+                "mixed_bf16_kkt_final": rbf.report["kkt"],
+                "mixed_bf16_vs_fp64_y_rel": float(np.max(np.abs(ybf - y64)) / np.max(np.abs(y64))),
+            })
+            log(f"mixed-bf16 comparison: {rbf.report['iters']} iters in {dtb:.3f} s")
 
     if args.constant_compare and rule == "adaptive":
         torch.cuda.synchronize()
