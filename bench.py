@@ -13,7 +13,8 @@ device memory before the timed region; outputs stay on the device.
 Prints one JSON line (stdout).  `value` is dual iterations per second over the timed fits
 (whole-fit wall time, preprocessing and stopping tests included); `ms_per_step` is the
 time-to-tolerance of one fit.  Extra fields compare the mixed-precision path with the plain
-FP64 path and with the BF16-high-part split form on the same input (context, not `value`),
+FP64 path and with the BF16-high-part split form on the same input, time the same workload on
+five more seeds (the adaptive trajectory, and so the time, varies by input; context, not `value`),
 report the roofline of the fused pass, and time the FP64 CPU
 oracle on the host cores on a bounded sample of the same fit.  After the timed fits the default run
 also reports the serving stream (512 requests: p50/p99 latency, fits/s), the continuation, the
@@ -415,6 +416,25 @@ def main() -> int:
                 "mixed_bf16_vs_fp64_y_rel": float(np.max(np.abs(ybf - y64)) / np.max(np.abs(y64))),
             })
             log(f"mixed-bf16 comparison: {rbf.report['iters']} iters in {dtb:.3f} s")
+
+    if not args.no_compare:
+        # the adaptive trajectory moves at rounding level with the input, so the time to tolerance
+        # of one seed is one sample of a spread: the same workload on five more seeds (context)
+        other = []
+        for sd in range(1, 6):
+            xo_h, ybo_h = W.make(WORKLOAD, seed=args.seed + sd)
+            xo = torch.from_numpy(xo_h).to(dev)
+            ybo = torch.from_numpy(ybo_h).to(dev)
+            opt = cr.Options(precision=args.precision, device=0, step_rule=rule, restart=restart,
+                             stream=torch.cuda.current_stream(dev).cuda_stream)
+            cr.fit(xo, ybo, wl.delta, args.tol, opt)   # warm (allocation, power iteration caches)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ro = cr.fit(xo, ybo, wl.delta, args.tol, opt)
+            torch.cuda.synchronize()
+            other.append((args.seed + sd, round(time.perf_counter() - t1, 4), ro.report["iters"]))
+        extra["other_seeds_seed_s_iters"] = other
+        log("other seeds: " + ", ".join(f"{a}: {b:.3f} s / {c} it" for a, b, c in other))
 
     if args.constant_compare and rule == "adaptive":
         torch.cuda.synchronize()
