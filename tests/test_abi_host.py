@@ -107,3 +107,25 @@ def test_continuation_rejects_bad_parameters_on_host(cr, field, value):
     rc = lib.cr_fit_continuation(4, 2, cr._ptr(x), cr._ptr(yb), C.byref(cp), C.byref(opt), cr._ptr(y), cr._ptr(xi),
                                  None, None, None)
     assert rc == cr.CR_EINVAL
+
+
+def test_no_device_fails_loudly(cr):
+    """Without a visible GPU a well-formed fit is refused with CR_EDEVICE: there is no CPU path."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except ImportError:
+        pass
+    lib = cr.load()
+    assert lib.cr_device_check(0) == cr.CR_EDEVICE
+    x = np.random.default_rng(0).uniform(-1.0, 1.0, size=(8, 2))
+    yb = (x ** 2).sum(axis=1)
+    y = np.zeros(8)
+    xi = np.zeros((8, 2))
+    opt = cr.Options().to_c()
+    rc = lib.cr_fit(8, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)
+    assert rc == cr.CR_EDEVICE
+    with pytest.raises(cr.CRError) as e:
+        cr.fit(x, yb, 1e-3, 1e-4)
+    assert e.value.code == cr.CR_EDEVICE
