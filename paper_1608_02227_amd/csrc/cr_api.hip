@@ -460,11 +460,13 @@ int cr_solver::prime() {
 // next extrapolated point eta(lam~^{k+1}) from them.  have_cur_in_yc: eta(lam^k) is already in
 // yc / xic / dmyc (fresh from a stopping test).
 int cr_solver::refresh_eta(bool have_cur_in_yc) {
-    const size_t nr = g.Nr, rows_np = (size_t)g.Nr * g.NP;
     if (have_cur_in_yc) {
-        CR_HIP(hipMemcpyAsync(ye[ecur], yc, nr * 8, hipMemcpyDeviceToDevice, stream));
-        CR_HIP(hipMemcpyAsync(xie[ecur], xic, rows_np * 8, hipMemcpyDeviceToDevice, stream));
-        CR_HIP(hipMemcpyAsync(dmye[ecur], dmyc, nr * 8, hipMemcpyDeviceToDevice, stream));
+        // take the test's buffers over instead of copying them; yc / xic / dmyc are then scratch
+        // until the next test fills them again, so that test's results are no longer reusable
+        std::swap(ye[ecur], yc);
+        std::swap(xie[ecur], xic);
+        std::swap(dmye[ecur], dmyc);
+        test_fresh = false;
     } else {
         int rc = adjoint_to(cur, ye[ecur], xie[ecur], dmye[ecur], false, nullptr, nullptr, nullptr);
         if (rc) return rc;
