@@ -491,3 +491,37 @@ def test_time_budget_and_zero_iteration_cap(cr, torch_dev):
     # at lam = 0 the fitted values are the observations and the slopes vanish
     np.testing.assert_array_equal(r0.y, ybar)
     assert np.all(r0.xi == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_adaptive_step_factor_three_matches_oracle(cr, torch_dev, precision):
+    """upsilon = 3 instead of the default 2: the accepted steps are L 3^m with the oracle's exponents
+    (the values agree to rounding: unlike powers of 2, the library's running products by 3 and the
+    oracle's s_{k-1} 3^(l-1) round differently), and the iterates agree to the FP64 bar (the
+    oracle's own spread) or the mixed bar."""
+    x, ybar = W.make("quad_N8000_n40", seed=4, N=160)
+    delta = W.WORKLOADS["quad_N8000_n40"].delta
+    L, _, _ = oracle.lipschitz(x, delta)
+    its, its_p, steps = [], [], []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=12, check_every=10 ** 9, iterates=its, adaptive=True,
+                upsilon=3.0, restart=True, steps=steps)
+    yp = ybar * (1.0 + 1e-15 * np.random.default_rng(4).standard_normal(len(ybar)))
+    oracle.papg(x, yp, delta, 0.0, L=L, max_iters=12, check_every=10 ** 9, iterates=its_p, adaptive=True,
+                upsilon=3.0, restart=True)
+    assert any(abs(math.log(s / L, 3) - round(math.log(s / L, 3))) < 1e-9 and s != L for s in steps)
+    with cr.Solver(x, ybar, delta, cr.Options(precision=precision, upsilon=3.0)) as s:
+        s.set_L(L)
+        s.iterate(12)
+        lam = s.lam()
+        rep = s.report()
+    ref, refp = its[-1][1], its_p[-1][1]
+    scale = np.abs(ref).max()
+    if precision == "fp64":
+        assert round(math.log(rep["step_final"] / L, 3)) == round(math.log(steps[-1] / L, 3))
+        assert rep["step_final"] == pytest.approx(steps[-1], rel=1e-12)
+        bar = max(1e-10, 100.0 * np.max(np.abs(refp - ref)) / scale)
+    else:
+        bar = 1e-4
+    e = math.log(rep["step_final"] / L, 3)
+    assert abs(e - round(e)) < 1e-9
+    assert np.max(np.abs(lam - ref)) <= bar * scale
