@@ -525,3 +525,25 @@ def test_adaptive_step_factor_three_matches_oracle(cr, torch_dev, precision):
     e = math.log(rep["step_final"] / L, 3)
     assert abs(e - round(e)) < 1e-9
     assert np.max(np.abs(lam - ref)) <= bar * scale
+
+
+@pytest.mark.parametrize("restart", [False, True])
+def test_adaptive_without_momentum_mixed_matches_oracle(cr, torch_dev, restart):
+    """Plain projected dual gradient ascent (momentum off: beta = 0 throughout, so the trial's
+    extrapolated point is the iterate itself) under the adaptive step in the split FP32 form:
+    10 iterates agree with the oracle to the mixed bar."""
+    x, ybar = W.make("lse8_N2000_n10", seed=3, N=130)
+    delta = 1e-3
+    L, _, _ = oracle.lipschitz(x, delta)
+    its = []
+    oracle.papg(x, ybar, delta, 0.0, L=L, max_iters=10, check_every=10 ** 9, iterates=its, adaptive=True,
+                momentum=False, restart=restart)
+    ref = its[-1][1]
+    with cr.Solver(x, ybar, delta, cr.Options(precision="mixed_fp32", momentum=False, restart=restart)) as s:
+        s.set_L(L)
+        s.iterate(10)
+        lam = s.lam()
+        rep = s.report()
+    assert np.max(np.abs(lam - ref)) <= 1e-4 * np.abs(ref).max()
+    assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
+    assert rep["adv_passes"] > 0
