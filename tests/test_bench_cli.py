@@ -67,3 +67,30 @@ def test_committed_traffic_file_is_well_formed(name):
     for k in t["kernels"].values():
         assert k["bytes_per_launch"] == pytest.approx(k["fetch_bytes"] + k["write_bytes"])
         assert k["bytes_per_launch"] >= k["algorithmic_bytes_per_launch"]
+
+
+def test_line_stays_short_and_keeps_the_contract():
+    """The driver keeps a bounded tail of stdout: the JSON line is cut to LINE_LIMIT characters by
+    dropping optional sections (named in the line), never the contract's fields."""
+    b = _bench()
+    core = {"metric": "m", "value": 1.0, "unit": "u", "n_gpus": 1, "steps": 2, "warmup": 1, "ms_per_step": 1.0,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic", "config": {"workload": "w"},
+            "roofline": {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 0.5,
+                         "traffic": None},
+            "cpu_baseline": {"value": 1.0, "unit": "u", "cores": 16, "kind": "oracle", "sample": "s"}}
+    short = b.render_line(core)
+    assert json.loads(short) == core
+    big = dict(core)
+    for key in b.OPTIONAL_ORDER:
+        big[key] = {"pad": "x" * 1500}
+    line = b.render_line(big)
+    assert len(line) <= b.LINE_LIMIT
+    got = json.loads(line)
+    for key in core:
+        assert got[key] == core[key]
+    assert got["dropped_for_length"] and all(k not in got for k in got["dropped_for_length"])
+    # sections are dropped in the stated order, and only as many as needed
+    kept = [k for k in b.OPTIONAL_ORDER if k in got]
+    assert got["dropped_for_length"] == [k for k in b.OPTIONAL_ORDER if k not in kept]
+    assert kept == b.OPTIONAL_ORDER[len(got["dropped_for_length"]):]
