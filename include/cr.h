@@ -174,6 +174,32 @@ int cr_fit_device(int64_t N, int64_t n, const double *x, const double *ybar, dou
                   cr_report *rep);
 
 /*
+ * cr_fit_device_noalloc - cr_fit_device without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, outputs and results as cr_fit_device (the same kernels in the same order, so
+ * the results are bitwise equal), with these differences:
+ *   - every device buffer of the fit is carved from a library-owned scratch array of
+ *     cr_noalloc_scratch_bytes() bytes (128 MiB) that each device the library runs on holds until
+ *     the process ends; a fit needing more (cr_noalloc_required_bytes) returns CR_ENOMEM before
+ *     any device work.  The limit is N of about 2,600 in the mixed modes and about 1,700 in FP64
+ *     with the adaptive step (n = 40).
+ *   - no device or pinned host memory is allocated and no stream or event is created: all device
+ *     work runs on opt->stream (NULL: the null stream); the pass-time fields of the report are 0.
+ *   - the mixed modes never promote to FP64 (opt->stall_checks is ignored): the promotion needs a
+ *     second, FP64 copy of the multipliers that the scratch does not hold.
+ *   - the scratch keeps the previous call's contents; each call clears what it uses before use.
+ *     Calls from several host threads on one device are serialized by the library (they would
+ *     otherwise race on the shared array); other devices and other processes have their own copy.
+ */
+int cr_fit_device_noalloc(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
+                          double tol, const cr_options *opt, double *y, double *xi, double *lambda,
+                          cr_report *rep);
+/* Size of the scratch array of cr_fit_device_noalloc, and the bytes of it one fit needs
+ * (0 for N = 1 or invalid arguments). */
+size_t cr_noalloc_scratch_bytes(void);
+size_t cr_noalloc_required_bytes(int64_t N, int64_t n, const cr_options *opt);
+
+/*
  * Continuation to the unregularized least-squares estimator (Section 2.4.1).
  *   eps_t = eps0 / beta^t (beta > 1), outer iteration t = 1..T uses the Tikhonov weight
  *   gamma_t = kappa_gamma eps_t and computes a delta_t-optimal dual solution, delta_t =

@@ -131,6 +131,9 @@ def load() -> C.CDLL:
         "cr_device_check": (C.c_int, [C.c_int]),
         "cr_fit": (C.c_int, [i64, i64, vp, vp, d, d, _P(CROptions), vp, vp, vp, _P(CRReport)]),
         "cr_fit_device": (C.c_int, [i64, i64, vp, vp, d, d, _P(CROptions), vp, vp, vp, _P(CRReport)]),
+        "cr_fit_device_noalloc": (C.c_int, [i64, i64, vp, vp, d, d, _P(CROptions), vp, vp, vp, _P(CRReport)]),
+        "cr_noalloc_scratch_bytes": (C.c_size_t, []),
+        "cr_noalloc_required_bytes": (C.c_size_t, [i64, i64, _P(CROptions)]),
         "cr_solver_create": (C.c_int, [i64, i64, vp, vp, d, _P(CROptions), vp, _P(vp)]),
         "cr_solver_destroy": (C.c_int, [vp]),
         "cr_solver_lipschitz": (C.c_int, [vp, _P(d), _P(d), _P(i32)]),
@@ -251,12 +254,17 @@ class FitResult:
 
 
 def fit(x, ybar, delta: float, tol: float, options: Options | None = None, return_lambda: bool = False,
-        allow_noconv: bool = True) -> FitResult:
-    """One complete fit (cr_fit / cr_fit_device).  Device tensors in -> device tensors out."""
+        allow_noconv: bool = True, no_alloc: bool = False) -> FitResult:
+    """One complete fit (cr_fit / cr_fit_device).  Device tensors in -> device tensors out.
+
+    ``no_alloc`` (device tensors only) calls cr_fit_device_noalloc: the fit runs in the library's
+    fixed scratch array instead of allocating device memory (outputs are still the caller's)."""
     lib = load()
     opt = options or Options()
     rep = CRReport()
     allow = (CR_OK, CR_ENOCONV) if allow_noconv else (CR_OK,)
+    if no_alloc and not _is_torch_device(x):
+        raise ValueError("no_alloc needs device tensors (cr_fit_device_noalloc)")
     if _is_torch_device(x):
         import torch
         x = x.contiguous().to(torch.float64)
@@ -269,7 +277,8 @@ def fit(x, ybar, delta: float, tol: float, options: Options | None = None, retur
             opt = Options(**{**opt.__dict__, "stream": torch.cuda.current_stream(x.device).cuda_stream,
                              "device": x.device.index or 0})
         co = opt.to_c()
-        code = lib.cr_fit_device(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(ybar.data_ptr()), delta, tol,
+        entry = lib.cr_fit_device_noalloc if no_alloc else lib.cr_fit_device
+        code = entry(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(ybar.data_ptr()), delta, tol,
                                  C.byref(co), C.c_void_p(y.data_ptr()), C.c_void_p(xi.data_ptr()),
                                  C.c_void_p(lam.data_ptr()) if lam is not None else None, C.byref(rep))
     else:
@@ -284,6 +293,15 @@ def fit(x, ybar, delta: float, tol: float, options: Options | None = None, retur
                           _ptr(lam) if lam is not None else None, C.byref(rep))
     _check(code, "cr_fit", allow)
     return FitResult(y, xi, lam, rep.as_dict(), code)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load().cr_noalloc_scratch_bytes())
+
+
+def noalloc_required_bytes(N: int, n: int, options: Options | None = None) -> int:
+    co = (options or Options()).to_c()
+    return int(load().cr_noalloc_required_bytes(N, n, C.byref(co)))
 
 
 def fit_continuation(x, ybar, eps0: float, beta: float, kappa_gamma: float, kappa_delta: float, T: int,

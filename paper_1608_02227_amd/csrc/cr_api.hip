@@ -102,6 +102,17 @@ extern "C" int cr_device_check(int device) {
 
 int cr_solver::alloc(void **p, size_t bytes) {
     if (bytes == 0) bytes = 256;
+    if (ws) {
+        // carve a 256-byte aligned piece of the workspace (counting mode only adds up the sizes)
+        const size_t at = (ws->off + 255) & ~(size_t)255;
+        if (!ws->counting && (at > ws->size || bytes > ws->size - at)) {
+            *p = nullptr;
+            return CR_ENOMEM;
+        }
+        *p = ws->counting ? nullptr : ws->base + at;
+        ws->off = at + bytes;
+        return CR_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -113,7 +124,7 @@ int cr_solver::alloc(void **p, size_t bytes) {
 }
 
 void cr_solver::release(void *p) {
-    if (!p) return;
+    if (!p || ws) return;
     for (size_t k = 0; k < owned.size(); ++k)
         if (owned[k] == p) {
             (void)hipFree(p);
@@ -128,7 +139,7 @@ cr_solver::~cr_solver() {
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
     for (void *p : owned) (void)hipFree(p);
-    if (h_scal) (void)hipHostFree(h_scal);
+    if (h_scal && h_owned) (void)hipHostFree(h_scal);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -158,9 +169,119 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
     return CR_OK;
 }
 
+// Every device buffer of a fit, in one list (so that a workspace can be sized by running it in
+// counting mode).  Needs g, rep, adaptive and fp32pass set.
+int cr_solver::allocate_state(int64_t N, int64_t n) {
+    const size_t nr = g.Nr, np = g.NP, rows_np = nr * np;
+    const size_t pairs_p = nr * g.ld;
+    const size_t lamsz = pairs_p * (rep == REP_F64 ? 8 : 4);
+#define CR_ALLOC(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
+    CR_ALLOC(lam[0], lamsz);
+    CR_ALLOC(lam[1], lamsz);
+    if (adaptive && rep == REP_F64) {
+        CR_ALLOC(lam[2], lamsz);
+        CR_ALLOC(lam[3], lamsz);
+    }
+    if (rep != REP_F64) {
+        CR_ALLOC(lam_hi, pairs_p * (rep == REP_SPLIT_F32 ? 4 : 2));
+        CR_ALLOC(ubase, nr * 8);
+        CR_ALLOC(wbase, rows_np * 8);
+    }
+    CR_ALLOC(xhat64, rows_np * 8);
+    CR_ALLOC(ybar64, nr * 8);
+    CR_ALLOC(y64, nr * 8);
+    CR_ALLOC(xi64, rows_np * 8);
+    CR_ALLOC(dmy64, nr * 8);
+    CR_ALLOC(yc, nr * 8);
+    CR_ALLOC(xic, rows_np * 8);
+    CR_ALLOC(dmyc, nr * 8);
+    CR_ALLOC(yr, nr * 8);
+    CR_ALLOC(xir, rows_np * 8);
+    CR_ALLOC(dmyr, nr * 8);
+    CR_ALLOC(rowred, nr * 2 * 8);
+    CR_ALLOC(part_acc, (size_t)g.chunks * rows_np * 8);
+    CR_ALLOC(part_col, (size_t)g.strips * g.ld * 8);
+    CR_ALLOC(part_red, (size_t)g.grid() * kRed * 8);
+    CR_ALLOC(part_min, (size_t)g.strips * g.ld * 8);
+    CR_ALLOC(part_arg, (size_t)g.strips * g.ld * 4);
+    CR_ALLOC(scal, 32 * 8);
+    CR_ALLOC(cpot[0], nr * 8);
+    CR_ALLOC(cpot[1], nr * 8);
+    CR_ALLOC(changed, (size_t)((g.Nr + 255) / 256) * 8);
+    if (adaptive) {
+        CR_ALLOC(part_acc2, (size_t)g.chunks * rows_np * 8);
+        CR_ALLOC(part_col2, (size_t)g.strips * g.ld * 8);
+        CR_ALLOC(block_part, (size_t)(g.Nr / 16) * 4 * 8);
+        CR_ALLOC(decision, 4 * 8);
+        CR_ALLOC(trial_out, 16 * 8);
+        for (int q = 0; q < 2; ++q) {
+            CR_ALLOC(uD[q], nr * 8);
+            CR_ALLOC(wD[q], rows_np * 8);
+            CR_ALLOC(ye[q], nr * 8);
+            CR_ALLOC(xie[q], rows_np * 8);
+            CR_ALLOC(dmye[q], nr * 8);
+        }
+    }
+    if (fp32pass) {
+        CR_ALLOC(xhat32, rows_np * 4);
+        CR_ALLOC(y32, nr * 4);
+        CR_ALLOC(xi32, rows_np * 4);
+        CR_ALLOC(dmy32, nr * 4);
+    }
+    if (deferred()) {
+        CR_ALLOC(yo64, nr * 8);
+        CR_ALLOC(xio64, rows_np * 8);
+        CR_ALLOC(dmyo64, nr * 8);
+        CR_ALLOC(yo32, nr * 4);
+        CR_ALLOC(xio32, rows_np * 4);
+        CR_ALLOC(dmyo32, nr * 4);
+    }
+    CR_ALLOC(in_x, (size_t)N * n * 8);
+    CR_ALLOC(in_y, (size_t)N * 8);
+    CR_ALLOC(in_mu, (size_t)n * 8);
+#undef CR_ALLOC
+    return CR_OK;
+}
+
+namespace {
+// Tiling and representation of a new solver (no device work).
+void configure(cr_solver *s, int64_t N, int64_t n, const cr_options &opt) {
+    s->device = opt.device;
+    s->opt = opt;
+    // workgroups resident at once: one per compute unit at the pass kernel's occupancy
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, opt.device) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    s->g = make_geometry((int)N, (int)n, cus);
+    s->precision = opt.precision;
+    s->rep = rep_of(opt.precision);
+    s->adaptive = opt.step_rule == 1;
+    s->upsilon = opt.upsilon;
+    s->fp32pass = opt.precision != CR_FP64;
+}
+}  // namespace
+
+size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt_in, int device) {
+    cr_options opt;
+    if (opt_in) opt = *opt_in; else cr_default_options(&opt);
+    opt.device = device;
+    if (validate(N, n, 1.0, &opt) != CR_OK || N < 2) return 0;
+    cr_solver probe;
+    configure(&probe, N, n, opt);
+    cr_workspace count;
+    count.counting = true;
+    probe.ws = &count;
+    if (probe.allocate_state(N, n) != CR_OK) return 0;
+    probe.ws = nullptr;
+    probe.device = -1;
+    return (count.off + 255) & ~(size_t)255;
+}
+
 // x, ybar: pointers of kind `on_device` (true: device memory on opt.device).
 int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
-                          const cr_options *opt_in, const double *lambda0, bool on_device, cr_solver **out) {
+                          const cr_options *opt_in, const double *lambda0, bool on_device, cr_solver **out,
+                          cr_workspace *ws, double *pinned_scal) {
     if (!out || !x || !ybar) return CR_EINVAL;
     *out = nullptr;
     cr_options opt;
@@ -182,22 +303,8 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     if (!all_finite(hx.data(), hx.size()) || !all_finite(hy.data(), hy.size())) return CR_EINVAL;
 
     cr_solver *s = new cr_solver();
-    s->device = opt.device;
-    s->opt = opt;
+    configure(s, N, n, opt);
     s->delta = delta;
-    {
-        // workgroups resident at once: one per compute unit at the pass kernel's occupancy
-        hipDeviceProp_t prop;
-        int cus = 256;
-        if (hipGetDeviceProperties(&prop, opt.device) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-        s->g = make_geometry((int)N, (int)n, cus);
-    }
-    s->precision = opt.precision;
-    s->rep = rep_of(opt.precision);
-    s->adaptive = opt.step_rule == 1;
-    s->upsilon = opt.upsilon;
-    s->fp32pass = opt.precision != CR_FP64;
     double ymin = hy[0], ymax = hy[0];
     for (double v : hy) { ymin = std::min(ymin, v); ymax = std::max(ymax, v); }
     s->scale = std::max(1.0, ymax - ymin);
@@ -205,93 +312,45 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     s->lam_zero = (lambda0 == nullptr);
 
     auto bail = [&](int code) { delete s; return code; };
-    if (opt.stream) {
+    if (opt.stream || ws) {
+        // a workspace fit creates no stream: it runs on the caller's (possibly the null stream)
         s->stream = static_cast<hipStream_t>(opt.stream);
         s->own_stream = false;
     } else {
         if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return bail(CR_EDEVICE);
         s->own_stream = true;
     }
-    if (hipHostMalloc((void **)&s->h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-        return bail(CR_ENOMEM);
+    if (pinned_scal) {
+        s->h_scal = pinned_scal;
+        s->h_pinned = true;
+    } else if (ws) {
+        s->h_scal = s->h_local;
+        s->h_pinned = false;
+    } else {
+        if (hipHostMalloc((void **)&s->h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return bail(CR_ENOMEM);
+        s->h_pinned = true;
+        s->h_owned = true;
+    }
     std::memset(s->h_scal, 0, 32 * sizeof(double));
-    if (hipEventCreate(&s->ev_a) != hipSuccess || hipEventCreate(&s->ev_b) != hipSuccess) return bail(CR_EDEVICE);
-    // a state larger than the free device memory is refused before any O(N^2) allocation
-    {
+    if (!ws) {
+        if (hipEventCreate(&s->ev_a) != hipSuccess || hipEventCreate(&s->ev_b) != hipSuccess) return bail(CR_EDEVICE);
+        // a state larger than the free device memory is refused before any O(N^2) allocation
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && cr_state_bytes(N, n, opt.precision, s->adaptive) > fr)
             return bail(CR_ENOMEM);
+    } else {
+        ws->off = 0;
+        ws->counting = false;
+        s->ws = ws;
     }
+    rc = s->allocate_state(N, n);
+    if (rc) return bail(rc);
 
     const Geometry &g = s->g;
     const size_t nr = g.Nr, np = g.NP, rows_np = nr * np;
     const size_t pairs_p = nr * g.ld;
     const size_t lamsz = pairs_p * (s->rep == REP_F64 ? 8 : 4);
-#define CR_ALLOC(ptr, bytes) do { int r_ = s->alloc((void **)&(ptr), (bytes)); if (r_) return bail(r_); } while (0)
-    CR_ALLOC(s->lam[0], lamsz);
-    CR_ALLOC(s->lam[1], lamsz);
-    if (s->adaptive && s->rep == REP_F64) {
-        CR_ALLOC(s->lam[2], lamsz);
-        CR_ALLOC(s->lam[3], lamsz);
-    }
-    if (s->rep != REP_F64) {
-        CR_ALLOC(s->lam_hi, pairs_p * (s->rep == REP_SPLIT_F32 ? 4 : 2));
-        CR_ALLOC(s->ubase, nr * 8);
-        CR_ALLOC(s->wbase, rows_np * 8);
-    }
-    CR_ALLOC(s->xhat64, rows_np * 8);
-    CR_ALLOC(s->ybar64, nr * 8);
-    CR_ALLOC(s->y64, nr * 8);
-    CR_ALLOC(s->xi64, rows_np * 8);
-    CR_ALLOC(s->dmy64, nr * 8);
-    CR_ALLOC(s->yc, nr * 8);
-    CR_ALLOC(s->xic, rows_np * 8);
-    CR_ALLOC(s->dmyc, nr * 8);
-    CR_ALLOC(s->yr, nr * 8);
-    CR_ALLOC(s->xir, rows_np * 8);
-    CR_ALLOC(s->dmyr, nr * 8);
-    CR_ALLOC(s->rowred, nr * 2 * 8);
-    CR_ALLOC(s->part_acc, (size_t)g.chunks * rows_np * 8);
-    CR_ALLOC(s->part_col, (size_t)g.strips * g.ld * 8);
-    CR_ALLOC(s->part_red, (size_t)g.grid() * kRed * 8);
-    CR_ALLOC(s->part_min, (size_t)g.strips * g.ld * 8);
-    CR_ALLOC(s->part_arg, (size_t)g.strips * g.ld * 4);
-    CR_ALLOC(s->scal, 32 * 8);
-    CR_ALLOC(s->cpot[0], nr * 8);
-    CR_ALLOC(s->cpot[1], nr * 8);
-    CR_ALLOC(s->changed, (size_t)((g.Nr + 255) / 256) * 8);
-    if (s->adaptive) {
-        CR_ALLOC(s->part_acc2, (size_t)g.chunks * rows_np * 8);
-        CR_ALLOC(s->part_col2, (size_t)g.strips * g.ld * 8);
-        CR_ALLOC(s->block_part, (size_t)(g.Nr / 16) * 4 * 8);
-        CR_ALLOC(s->decision, 4 * 8);
-        for (int q = 0; q < 2; ++q) {
-            CR_ALLOC(s->uD[q], nr * 8);
-            CR_ALLOC(s->wD[q], rows_np * 8);
-            CR_ALLOC(s->ye[q], nr * 8);
-            CR_ALLOC(s->xie[q], rows_np * 8);
-            CR_ALLOC(s->dmye[q], nr * 8);
-        }
-    }
-    if (s->fp32pass) {
-        CR_ALLOC(s->xhat32, rows_np * 4);
-        CR_ALLOC(s->y32, nr * 4);
-        CR_ALLOC(s->xi32, rows_np * 4);
-        CR_ALLOC(s->dmy32, nr * 4);
-    }
-    if (s->deferred()) {
-        CR_ALLOC(s->yo64, nr * 8);
-        CR_ALLOC(s->xio64, rows_np * 8);
-        CR_ALLOC(s->dmyo64, nr * 8);
-        CR_ALLOC(s->yo32, nr * 4);
-        CR_ALLOC(s->xio32, rows_np * 4);
-        CR_ALLOC(s->dmyo32, nr * 4);
-    }
-    double *dx = nullptr, *dyb = nullptr, *dmu = nullptr;
-    CR_ALLOC(dx, hx.size() * 8);
-    CR_ALLOC(dyb, hy.size() * 8);
-    CR_ALLOC(dmu, (size_t)n * 8);
-#undef CR_ALLOC
 
     // Mixed modes work in the frame x - mean(x): every constraint and the adjoint depend only
     // on differences x_i - x_j, so (y, xi, lam) are unchanged while the float residual loses
@@ -307,10 +366,13 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     if (!s->fp32pass) std::fill(mu.begin(), mu.end(), 0.0);   // the FP64 mode keeps the caller's frame
     int rc2 = CR_OK;
     auto H = [&](hipError_t e) { if (e != hipSuccess && rc2 == CR_OK) rc2 = fail_hip(e, "setup"); };
-    H(hipMemcpyAsync(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, s->stream));
-    H(hipMemcpyAsync(dyb, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, s->stream));
-    H(hipMemcpyAsync(dmu, mu.data(), mu.size() * 8, hipMemcpyHostToDevice, s->stream));
-    H(launch_prepare(g, dx, dyb, s->fp32pass ? dmu : nullptr, s->xhat64, s->xhat32, s->ybar64, s->stream));
+    // a workspace keeps whatever the previous fit left there: clear all of it first
+    if (ws) H(launch_fill_zero(ws->base, ws->off, s->stream));
+    H(hipMemcpyAsync(s->in_x, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, s->stream));
+    H(hipMemcpyAsync(s->in_y, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, s->stream));
+    H(hipMemcpyAsync(s->in_mu, mu.data(), mu.size() * 8, hipMemcpyHostToDevice, s->stream));
+    H(launch_prepare(g, s->in_x, s->in_y, s->fp32pass ? s->in_mu : nullptr, s->xhat64, s->xhat32, s->ybar64,
+                     s->stream));
     // multipliers: lam^0 in both buffers (lam^{-1} := lam^0 makes the first extrapolation exact)
     if (lambda0) {
         double *dl = nullptr;
@@ -327,25 +389,27 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         H(hipMemcpyAsync(s->lam[1], s->lam[0], lamsz, hipMemcpyDeviceToDevice, s->stream));
         H(hipStreamSynchronize(s->stream));
         s->release(dl);
-    } else {
-        H(hipMemsetAsync(s->lam[0], 0, lamsz, s->stream));
-        H(hipMemsetAsync(s->lam[1], 0, lamsz, s->stream));
-        if (s->lam_hi) H(hipMemsetAsync(s->lam_hi, 0, pairs_p * (s->rep == REP_SPLIT_F32 ? 4 : 2), s->stream));
+    } else if (!ws) {
+        H(launch_fill_zero(s->lam[0], lamsz, s->stream));
+        H(launch_fill_zero(s->lam[1], lamsz, s->stream));
+        if (s->lam_hi) H(launch_fill_zero(s->lam_hi, pairs_p * (s->rep == REP_SPLIT_F32 ? 4 : 2), s->stream));
     }
-    if (s->ubase) {
-        H(hipMemsetAsync(s->ubase, 0, nr * 8, s->stream));
-        H(hipMemsetAsync(s->wbase, 0, rows_np * 8, s->stream));
-    }
-    H(hipMemsetAsync(s->part_acc, 0, (size_t)g.chunks * rows_np * 8, s->stream));
-    H(hipMemsetAsync(s->part_col, 0, (size_t)g.strips * g.ld * 8, s->stream));
-    if (s->adaptive) {
-        H(hipMemsetAsync(s->part_acc2, 0, (size_t)g.chunks * rows_np * 8, s->stream));
-        H(hipMemsetAsync(s->part_col2, 0, (size_t)g.strips * g.ld * 8, s->stream));
+    if (!ws) {
+        if (s->ubase) {
+            H(launch_fill_zero(s->ubase, nr * 8, s->stream));
+            H(launch_fill_zero(s->wbase, rows_np * 8, s->stream));
+        }
+        H(launch_fill_zero(s->part_acc, (size_t)g.chunks * rows_np * 8, s->stream));
+        H(launch_fill_zero(s->part_col, (size_t)g.strips * g.ld * 8, s->stream));
+        if (s->adaptive) {
+            H(launch_fill_zero(s->part_acc2, (size_t)g.chunks * rows_np * 8, s->stream));
+            H(launch_fill_zero(s->part_col2, (size_t)g.strips * g.ld * 8, s->stream));
+        }
     }
     H(hipStreamSynchronize(s->stream));
-    s->release(dx);
-    s->release(dyb);
-    s->release(dmu);
+    s->release(s->in_x);
+    s->release(s->in_y);
+    s->release(s->in_mu);
     if (rc2) return bail(rc2);
     *out = s;
     return CR_OK;
@@ -553,7 +617,7 @@ int cr_solver::step_adaptive() {
         }
         // the timed launches are the dominant kind: re-forming trials (split) or storing trials;
         // one in four is sampled
-        const bool timed = !ev_pending && (adv || !defer) && (timing_tick++ % 4 == 0);
+        const bool timed = ev_a && !ev_pending && (adv || !defer) && (timing_tick++ % 4 == 0);
         if (timed) CR_HIP(hipEventRecord(ev_a, stream));
         CR_HIP(launch_pass(g, adv ? PASS_ADV : (defer ? PASS_TRIAL_NS : PASS_TRIAL), fp32pass, rep, a, stream));
         if (timed) {
@@ -586,7 +650,9 @@ int cr_solver::step_adaptive() {
         // the test and the update.  Its outputs go to the pass-array set that becomes current on
         // acceptance (split forms keep this trial's set for re-forming the candidate).
         const TrialRule rule{sa, sb, delta, t, opt.restart ? 1 : 0, opt.momentum ? 1 : 0};
-        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_scal, h_seq(), seq, rule, decision, stream));
+        // without pinned host memory the scalars land in device memory and are copied back below
+        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_pinned ? h_scal : trial_out,
+                                   h_pinned ? h_seq() : nullptr, seq, rule, decision, stream));
         {
             const int en = 1 - ecur;
             double *yn = defer ? yo64 : y64, *xin = defer ? xio64 : xi64, *dmyn = defer ? dmyo64 : dmy64;
@@ -596,9 +662,12 @@ int cr_solver::step_adaptive() {
             CR_HIP(launch_accept(g, y64, xi64, yn, xin, dmyn, uD, wD, ye[ecur], xie[ecur], ye[en], xie[en], dmye[en],
                                  y32n, xi32n, dmy32n, xhat64, 1.0 / delta, 0.0, decision, stream));
         }
-        {
+        if (h_pinned) {
             const int rc = wait_trial(seq);
             if (rc) return rc;
+        } else {
+            CR_HIP(hipMemcpyAsync(h_scal, trial_out, 12 * sizeof(double), hipMemcpyDeviceToHost, stream));
+            CR_HIP(hipStreamSynchronize(stream));
         }
         collect_timing();
         trials += 2.0;
@@ -671,7 +740,7 @@ int cr_solver::step_once() {
     } else {
         a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
     }
-    const bool timed = !ev_pending;
+    const bool timed = ev_a && !ev_pending;
     if (timed) CR_HIP(hipEventRecord(ev_a, stream));
     CR_HIP(launch_pass(g, PASS_STEP, fp32pass, rep, a, stream));
     if (timed) {
@@ -822,7 +891,7 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
         // reuses the column minima above, offsets 0)
         const int nb = (g.Nr + 255) / 256;
         double *cin = cpot[0], *cout = cpot[1];
-        CR_HIP(hipMemsetAsync(cin, 0, (size_t)g.Nr * 8, stream));
+        CR_HIP(launch_fill_zero(cin, (size_t)g.Nr * 8, stream));
         own_converged = false;
         own_rounds = 0;
         for (int round = 1; round <= kOwnRounds; ++round) {
@@ -896,6 +965,7 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
 int cr_solver::promote() {
     test_fresh = false;
     if (rep == REP_F64) return CR_OK;
+    if (ws) return CR_ENOMEM;   // a workspace holds no room for the FP64 copy
     CR_HIP(hipSetDevice(device));
     int rc0 = materialize();
     if (rc0) return rc0;
@@ -971,9 +1041,10 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
         if ((by_gap ? rep.cert_gap : rep.kkt) <= tol) { status = CR_OK; break; }
         if (k >= kmax) break;
         if (opt.time_budget_s > 0.0 && now_s() - t0 > opt.time_budget_s) break;
-        if (fp32pass) {
+        if (fp32pass && !ws) {
             // safety net only: the split representation tracks FP64 to ~1e-9 in y, so a switch
-            // happens only after `stall_checks` tests without any new lowest residual
+            // happens only after `stall_checks` tests without any new lowest residual (not in a
+            // workspace, which holds no room for the FP64 copy)
             if (rep.kkt < best) { best = rep.kkt; since_best = 0; }
             else if (++since_best >= opt.stall_checks) {
                 rc = promote();
@@ -1118,6 +1189,10 @@ static int primal_out(cr_solver *s, const double *ysrc, const double *xisrc, dou
     double *dy = nullptr, *dxi = nullptr;
     if (device_out) {
         dy = y; dxi = xi;
+    } else if (s->ws) {
+        // a workspace fit stages the dense copies in its scratch primal buffers (N <= Nr and
+        // N n <= Nr NP), which nothing reads after the fit
+        dy = s->yr; dxi = s->xir;
     } else {
         int rc = s->alloc((void **)&dy, N * 8);
         if (rc) return rc;
@@ -1130,7 +1205,7 @@ static int primal_out(cr_solver *s, const double *ysrc, const double *xisrc, dou
         CR_HIP(hipMemcpyAsync(xi, dxi, N * n * 8, hipMemcpyDeviceToHost, s->stream));
     }
     CR_HIP(hipStreamSynchronize(s->stream));
-    if (!device_out) {
+    if (!device_out && !s->ws) {
         s->release(dy);
         s->release(dxi);
     }
@@ -1179,8 +1254,9 @@ static int fit_trivial(int64_t N, int64_t n, const double *ybar, double *y, doub
     return CR_OK;
 }
 
-static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
-                    const cr_options *opt_in, double *y, double *xi, double *lambda, cr_report *rep, bool dev) {
+int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+                const cr_options *opt_in, double *y, double *xi, double *lambda, cr_report *rep, bool dev,
+                cr_workspace *ws, double *pinned_scal) {
     const double t0 = now_s();
     cr_options opt;
     if (opt_in) opt = *opt_in; else cr_default_options(&opt);
@@ -1190,7 +1266,7 @@ static int fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, d
     if (!(tol > 0.0) || !std::isfinite(tol)) return CR_EINVAL;
     if (N == 1) return fit_trivial(N, n, ybar, y, xi, lambda, rep, dev, opt);
     cr_solver *s = nullptr;
-    rc = cr_solver_create_impl(N, n, x, ybar, delta, &opt, nullptr, dev, &s);
+    rc = cr_solver_create_impl(N, n, x, ybar, delta, &opt, nullptr, dev, &s, ws, pinned_scal);
     if (rc) return rc;
     if (opt.L > 0.0) { s->L = opt.L; s->s_step = opt.L; }
     cr_report r;
@@ -1296,12 +1372,12 @@ extern "C" int cr_fit_continuation(int64_t N, int64_t n, const double *x, const 
 
 extern "C" int cr_fit(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
                       const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep) {
-    return fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, false);
+    return cr_fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, false);
 }
 
 extern "C" int cr_fit_device(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
                              const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep) {
-    return fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, true);
+    return cr_fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, true);
 }
 
 // ---- operators --------------------------------------------------------------------------------

@@ -6,6 +6,16 @@
 
 #include <vector>
 
+// Caller-provided device memory for one solver: every device buffer of the fit is carved from
+// [base, base + size) in 256-byte aligned pieces instead of being allocated.  With `counting` set
+// nothing is carved; `off` only adds up what the fit would take.
+struct cr_workspace {
+    char *base = nullptr;
+    size_t size = 0;
+    size_t off = 0;
+    bool counting = false;
+};
+
 struct cr_solver {
     cr::Geometry g{};
     int device = -1;
@@ -72,6 +82,16 @@ struct cr_solver {
     unsigned long long *h_seq() const { return reinterpret_cast<unsigned long long *>(h_scal + 24); }
     int wait_trial(unsigned long long seq);
     std::vector<void *> owned;
+    // Workspace mode (set before the state is allocated): buffers come from `ws`, release() does
+    // nothing, no events are created (no pass timing), and the FP64 promotion is off (it would need
+    // a second, FP64 copy of the multipliers).  Without pinned host memory (`h_pinned` false)
+    // the trial scalars are read back by a copy and a stream synchronization instead of polling.
+    cr_workspace *ws = nullptr;
+    bool h_pinned = true;
+    bool h_owned = false;           // h_scal was allocated by the solver (hipHostMalloc)
+    double *in_x = nullptr, *in_y = nullptr, *in_mu = nullptr;   // input staging (set-up only)
+    double h_local[32] = {};
+    double *trial_out = nullptr;    // device copy of the trial scalars when h_scal is not pinned
 
     // iteration state
     double L = 0.0, sigma2 = 0.0, preprocess_s = 0.0;
@@ -98,6 +118,7 @@ struct cr_solver {
 
     ~cr_solver();
     int alloc(void **p, size_t bytes);
+    int allocate_state(int64_t N, int64_t n);   // every device buffer of the fit
     void release(void *p);
     int adjoint_to(int idx, double *y, double *xi, double *dmy, bool with_rowred, float *y32_, float *xi32_,
                    float *dmy32_);
@@ -113,8 +134,19 @@ struct cr_solver {
     int solve(double tol, cr_report *rep);
 };
 
+// ws: optional workspace (see cr_workspace); pinned_scal: optional host array of 32 doubles in
+// pinned memory for the scalar read-backs (null: the solver allocates its own, or, in workspace
+// mode, uses an unpinned array of its own).
 int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta,
-                          const cr_options *opt, const double *lambda0, bool on_device, cr_solver **out);
+                          const cr_options *opt, const double *lambda0, bool on_device, cr_solver **out,
+                          cr_workspace *ws = nullptr, double *pinned_scal = nullptr);
+// Device bytes a fit of this shape and these options takes from a workspace (exact, including the
+// 256-byte alignment of every piece); 0 if the arguments are invalid.
+size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt, int device);
+// One complete fit (the body of cr_fit / cr_fit_device), optionally inside a workspace.
+int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
+                const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep, bool dev,
+                cr_workspace *ws = nullptr, double *pinned_scal = nullptr);
 size_t cr_state_bytes(int64_t N, int64_t n, int precision, bool adaptive);
 
 namespace cr {

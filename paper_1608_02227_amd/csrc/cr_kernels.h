@@ -243,6 +243,10 @@ hipError_t launch_relax_finish(const Geometry &g, const double *part_min, const 
                                const double *y, const double *xi, const double *ybar, double xspan,
                                double *rowred, double *changed, hipStream_t st);
 
+// Sets `bytes` bytes at p (256-byte aligned) to zero with a plain fill kernel (no memset node, so
+// the clear also replays correctly where a caller captures the stream into a graph).
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+
 // Copies the FP64 y (Nr) and xi (Nr x NP) to dense N and N x n arrays.
 hipError_t launch_unpad_primal(const Geometry &g, const double *y, const double *xi,
                                double *y_out, double *xi_out, hipStream_t st);

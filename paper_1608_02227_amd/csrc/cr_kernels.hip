@@ -25,6 +25,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace cr {
@@ -1218,6 +1219,22 @@ hipError_t launch_repair_finish(const Geometry &g, const double *part_min, const
                                 double *rowred, double xspan, hipStream_t st) {
     hipLaunchKernelGGL(repair_finish_kernel, dim3((g.Nr + 255) / 256), dim3(256), 0, st, part_min, part_arg, y, xi,
                        ybar, y_rep, xi_rep, rowred, xspan, g.N, g.Nr, g.ld, g.strips, g.NP);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint4 *p, size_t n16, uint8_t *tail, int ntail) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += stride) p[e] = uint4{0, 0, 0, 0};
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    const size_t n16 = bytes / 16;
+    const int ntail = (int)(bytes - n16 * 16);
+    const size_t blocks = std::min<size_t>(4096, std::max<size_t>(1, (n16 + 255) / 256));
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint4 *>(p), n16,
+                       static_cast<uint8_t *>(p) + n16 * 16, ntail);
     return hipGetLastError();
 }
 

@@ -129,3 +129,40 @@ def test_no_device_fails_loudly(cr):
     with pytest.raises(cr.CRError) as e:
         cr.fit(x, yb, 1e-3, 1e-4)
     assert e.value.code == cr.CR_EDEVICE
+
+
+def test_noalloc_sizes_on_host(cr):
+    """The allocation-free fit's scratch and what a fit needs of it (host arithmetic, no GPU): the
+    need grows with N, stays within the scratch at the stated limits (N = 2,600 mixed, 1,700 FP64
+    with the adaptive step, n = 40) and exceeds it beyond; N = 1 needs nothing."""
+    total = cr.noalloc_scratch_bytes()
+    assert total == 128 << 20
+    mixed = cr.Options(precision="mixed_fp32")
+    fp64 = cr.Options(precision="fp64")
+    assert cr.noalloc_required_bytes(1, 3, mixed) == 0
+    sizes = [cr.noalloc_required_bytes(N, 40, mixed) for N in (100, 1000, 2000, 2600)]
+    assert all(0 < a < b for a, b in zip(sizes, sizes[1:]))
+    assert sizes[-1] <= total < cr.noalloc_required_bytes(2800, 40, mixed)
+    assert cr.noalloc_required_bytes(1700, 40, fp64) <= total < cr.noalloc_required_bytes(1800, 40, fp64)
+    # every piece is 256-byte aligned, so the total is a multiple of 256 and at least the multipliers
+    assert all(s % 256 == 0 for s in sizes)
+    assert sizes[2] >= 2048 * 2048 * 12
+    assert cr.noalloc_required_bytes(10, 64, mixed) == 0      # n + 1 > 64 is invalid
+
+
+def test_noalloc_without_device_fails_loudly(cr):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except ImportError:
+        pass
+    lib = cr.load()
+    x = np.random.default_rng(0).uniform(-1.0, 1.0, size=(8, 2))
+    yb = (x ** 2).sum(axis=1)
+    y = np.zeros(8)
+    xi = np.zeros((8, 2))
+    opt = cr.Options().to_c()
+    rc = lib.cr_fit_device_noalloc(8, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi),
+                                   None, None)
+    assert rc == cr.CR_EDEVICE
