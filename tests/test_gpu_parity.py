@@ -142,23 +142,41 @@ def _golden(name):
         return json.load(f)
 
 
-# Converged fits follow the oracle's trajectory iterate by iterate (1e-15 per step), but over
-# tens of thousands of momentum steps summation-order differences move the trajectory: the
-# N=200, n=2 fit (65,800 iterations to KKT 1e-4) ends 1.0e-5 apart in y (relative) at the same
-# stopping iteration, the N=400, n=10 fit (11,650 iterations) within 1e-6.  The bars below are
-# those measured drifts with headroom; the FP64 1e-6 bar itself is checked at 5,000 iterations.
-@pytest.mark.parametrize("name,ybar_rel", [("sqnorm_N200_n2_seed0_tol1e-4", 3e-5),
-                                           ("lse8_N400_n10_seed1_tol1e-4", 1e-6)])
-def test_converged_fit_fp64_matches_oracle(cr, torch_dev, name, ybar_rel):
-    gd = _golden(name)
+# Constant step (the paper's PAPG_C) in FP64 against the oracle's constant-step run with the same L
+# and test schedule: both stop at the same iteration, and the fitted values agree to the FP64 bar.
+def test_converged_fit_fp64_matches_oracle(cr, torch_dev):
+    gd = _golden("lse8_N400_n10_seed1_tol1e-4")
     x, ybar = W.make(gd["workload"], seed=gd["seed"], N=gd["N"])
     opt = cr.Options(L=gd["L"], check_every=gd["check_every"], step_rule="constant", checks="fixed")
     r = cr.fit(x, ybar, gd["delta"], gd["tol"], opt, allow_noconv=False)
     assert r.report["kkt"] <= gd["tol"]
-    y_ref = np.array(gd["y"])
-    assert _rel(r.y, y_ref) <= ybar_rel
+    assert _rel(r.y, np.array(gd["y"])) <= 1e-6
     assert abs(r.report["iters"] - gd["iters"]) <= gd["check_every"]
     assert r.report["y_err_bound"] >= 0.0 and r.report["cert_gap"] >= 0.0
+
+
+def test_constant_step_fit_within_its_certificate_of_the_optimum(cr, torch_dev):
+    """The N=200, n=2 configuration with the constant step (65,800 iterations to KKT 1e-4).  Over tens
+    of thousands of momentum steps, summation-order differences move the trajectory (two FP64 runs
+    stop at the same iteration ~1e-5 apart in y), and the constant step's KKT residual is still
+    4e-6 after 400,000 oracle iterations, so no converged constant-step reference exists at the 1e-6
+    bar: the per-step arithmetic is pinned at 5,000 iterations below, and the converged fit is
+    checked against the unique optimum.  The oracle's fit converged to KKT 1e-10 (tests/golden,
+    restarted adaptive step) pins y*, and by Theorem thm:rate the GPU fit lies within sqrt(2 G) of
+    it for its certified gap G."""
+    gd = _golden("sqnorm_N200_n2_seed0_tol1e-4")
+    x, ybar = W.make(gd["workload"], seed=gd["seed"], N=gd["N"])
+    d = np.load(os.path.join(GOLDEN, "c1_sqnorm_N200_n2_seed0_tol1e-10.npz"), allow_pickle=False)
+    y_ref, G_ref = d["y"], json.loads(str(d["meta"]))["cert_gap"]
+    opt = cr.Options(L=gd["L"], check_every=gd["check_every"], step_rule="constant", checks="fixed")
+    r = cr.fit(x, ybar, gd["delta"], gd["tol"], opt, allow_noconv=False)
+    assert r.report["kkt"] <= gd["tol"]
+    assert abs(r.report["iters"] - gd["iters"]) <= gd["check_every"]
+    G = r.report["cert_gap"]
+    assert G >= 0.0
+    assert np.linalg.norm(r.y - y_ref) <= math.sqrt(2.0 * G) + math.sqrt(2.0 * G_ref)
+    # the oracle's own constant-step fit obeys the same bound (it stopped at the same iteration)
+    assert np.linalg.norm(np.array(gd["y"]) - y_ref) <= math.sqrt(2.0 * gd["cert_gap"]) + math.sqrt(2.0 * G_ref)
 
 
 def test_fp64_fit_values_at_5000_iterations(cr, torch_dev):
