@@ -46,6 +46,7 @@ extern "C" {
 #define CR_EDEVICE (-5)  /* a HIP call failed, or no gfx950 device */
 #define CR_EAGAIN (-6)   /* serving: the request has not finished yet */
 #define CR_ENOTFOUND (-7)/* serving: unknown request id */
+#define CR_ECANCELED (-8)/* serving: the context was destroyed before the request ran */
 
 /* Arithmetic of the multiplier state and of the pair pass. */
 typedef enum {
@@ -185,8 +186,9 @@ int cr_fit_device(int64_t N, int64_t n, const double *x, const double *ybar, dou
  *     with the adaptive step (n = 40).
  *   - no device or pinned host memory is allocated and no stream or event is created: all device
  *     work runs on opt->stream (NULL: the null stream); the pass-time fields of the report are 0.
- *   - the mixed modes never promote to FP64 (opt->stall_checks is ignored): the promotion needs a
- *     second, FP64 copy of the multipliers that the scratch does not hold.
+ *   - the mixed modes promote to FP64 (the stalled-fit safety net) only if the rest of the scratch
+ *     holds the FP64 copy of the multipliers (N up to about 1,500 at n = 40); otherwise they keep
+ *     the split form.
  *   - the scratch keeps the previous call's contents; each call clears what it uses before use.
  *     Calls from several host threads on one device are serialized by the library (they would
  *     otherwise race on the shared array); other devices and other processes have their own copy.
@@ -298,9 +300,14 @@ int cr_op_adjoint(int64_t N, int64_t n, const double *x, const double *lam, doub
 /* ---- Serving: continuous batching of fits on one device. --------------------------------- */
 typedef struct cr_ctx cr_ctx;
 
-/* byte_budget: device bytes the resident multiplier state of all admitted fits may use
- * (0 = 80% of free device memory); max_slots: fits resident at once. */
+/* byte_budget: device bytes the resident state of all admitted fits may use (0 = 80% of free
+ * device memory); max_slots: fits resident at once.  Each slot owns a stream, a small pinned
+ * host buffer and a device arena that grows to the largest fit the slot has run and is then
+ * reused (fits allocate nothing while the arena is large enough); the arenas are freed by
+ * cr_ctx_destroy. */
 int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, cr_ctx **out);
+/* Running fits finish; queued ones are dropped and their waiters (cr_wait) return CR_ECANCELED.
+ * Returns once no thread is inside a call on ctx any more; ctx is then invalid. */
 int cr_ctx_destroy(cr_ctx *ctx);
 /* Queues a fit (copies x, ybar); non-blocking.  Returns its id in *req_id. */
 int cr_submit(cr_ctx *ctx, int64_t N, int64_t n, const double *x, const double *ybar,
@@ -311,9 +318,10 @@ int cr_poll(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
 /* Blocking version of cr_poll. */
 int cr_wait(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
             double *latency_s);
-/* Device bytes the serving context reserves for one fit of this shape and precision (the two
- * multiplier iterates, the partial sums and O(N n) vectors; mixed modes include the FP64 pair a
- * promotion would allocate).  Admission requires the sum over running fits to fit the budget. */
+/* Device bytes the serving context reserves for one fit of this shape and precision with the
+ * default step rule (its whole device state: the multiplier iterates, the partial sums and the
+ * O(N n) vectors; mixed modes include the FP64 copy a promotion would take).  Admission requires
+ * the sum over running fits to fit the budget. */
 size_t cr_fit_state_bytes(int64_t N, int64_t n, int32_t precision);
 
 /* Counters: fits queued, running, finished; bytes of multiplier state resident. */

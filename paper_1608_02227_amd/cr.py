@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CR_LIB_PATH") or os.path.join(_HERE, "libcr.so")
 
 CR_OK, CR_EINVAL, CR_ENOMEM, CR_ENOCONV, CR_ENUMERIC, CR_EDEVICE, CR_EAGAIN, CR_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
+CR_ECANCELED = -8
 PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
 
 

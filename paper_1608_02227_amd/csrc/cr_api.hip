@@ -83,6 +83,7 @@ extern "C" const char *cr_strerror(int code) {
     case CR_EDEVICE: return "HIP device error or no gfx950 device";
     case CR_EAGAIN: return "request still running";
     case CR_ENOTFOUND: return "unknown request id";
+    case CR_ECANCELED: return "request dropped: the serving context was destroyed before it ran";
     default: return "unknown error";
     }
 }
@@ -262,7 +263,7 @@ void configure(cr_solver *s, int64_t N, int64_t n, const cr_options &opt) {
 }
 }  // namespace
 
-size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt_in, int device) {
+size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt_in, int device, bool promotion) {
     cr_options opt;
     if (opt_in) opt = *opt_in; else cr_default_options(&opt);
     opt.device = device;
@@ -275,7 +276,10 @@ size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt_in, int de
     if (probe.allocate_state(N, n) != CR_OK) return 0;
     probe.ws = nullptr;
     probe.device = -1;
-    return (count.off + 255) & ~(size_t)255;
+    size_t b = (count.off + 255) & ~(size_t)255;
+    if (promotion && probe.rep != REP_F64)
+        b += (probe.adaptive ? 4 : 2) * (((size_t)probe.g.Nr * probe.g.ld * 8 + 255) & ~(size_t)255);
+    return b;
 }
 
 // x, ybar: pointers of kind `on_device` (true: device memory on opt.device).
@@ -965,12 +969,15 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
 int cr_solver::promote() {
     test_fresh = false;
     if (rep == REP_F64) return CR_OK;
-    if (ws) return CR_ENOMEM;   // a workspace holds no room for the FP64 copy
+    const size_t bytes = (size_t)g.Nr * g.ld * 8;
+    const int nbuf = adaptive ? 4 : 2;
+    // a workspace promotes only if the FP64 copy fits in what is left of it (checked before any
+    // work, so that a refusal leaves the split state untouched)
+    if (ws && (((ws->off + 255) & ~(size_t)255) + nbuf * ((bytes + 255) & ~(size_t)255) > ws->size))
+        return CR_ENOMEM;
     CR_HIP(hipSetDevice(device));
     int rc0 = materialize();
     if (rc0) return rc0;
-    const size_t bytes = (size_t)g.Nr * g.ld * 8;
-    const int nbuf = adaptive ? 4 : 2;
     void *nb[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int q = 0; q < nbuf; ++q) {
         int rc = alloc(&nb[q], bytes);
@@ -1041,14 +1048,14 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
         if ((by_gap ? rep.cert_gap : rep.kkt) <= tol) { status = CR_OK; break; }
         if (k >= kmax) break;
         if (opt.time_budget_s > 0.0 && now_s() - t0 > opt.time_budget_s) break;
-        if (fp32pass && !ws) {
+        if (fp32pass) {
             // safety net only: the split representation tracks FP64 to ~1e-9 in y, so a switch
-            // happens only after `stall_checks` tests without any new lowest residual (not in a
-            // workspace, which holds no room for the FP64 copy)
+            // happens only after `stall_checks` tests without any new lowest residual (a workspace
+            // without room for the FP64 copy keeps the split form)
             if (rep.kkt < best) { best = rep.kkt; since_best = 0; }
             else if (++since_best >= opt.stall_checks) {
                 rc = promote();
-                if (rc) return rc;
+                if (rc && !(rc == CR_ENOMEM && ws)) return rc;
                 best = INFINITY;
                 since_best = 0;
             }

@@ -83,8 +83,8 @@ struct cr_solver {
     int wait_trial(unsigned long long seq);
     std::vector<void *> owned;
     // Workspace mode (set before the state is allocated): buffers come from `ws`, release() does
-    // nothing, no events are created (no pass timing), and the FP64 promotion is off (it would need
-    // a second, FP64 copy of the multipliers).  Without pinned host memory (`h_pinned` false)
+    // nothing, no events are created (no pass timing), and the FP64 promotion takes place only if
+    // the rest of the workspace holds the FP64 copy of the multipliers.  Without pinned host memory (`h_pinned` false)
     // the trial scalars are read back by a copy and a stream synchronization instead of polling.
     cr_workspace *ws = nullptr;
     bool h_pinned = true;
@@ -141,8 +141,9 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
                           const cr_options *opt, const double *lambda0, bool on_device, cr_solver **out,
                           cr_workspace *ws = nullptr, double *pinned_scal = nullptr);
 // Device bytes a fit of this shape and these options takes from a workspace (exact, including the
-// 256-byte alignment of every piece); 0 if the arguments are invalid.
-size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt, int device);
+// 256-byte alignment of every piece), with `promotion` also the FP64 copy a mixed-precision fit
+// takes if it promotes; 0 if the arguments are invalid.
+size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt, int device, bool promotion = false);
 // One complete fit (the body of cr_fit / cr_fit_device), optionally inside a workspace.
 int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
                 const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep, bool dev,

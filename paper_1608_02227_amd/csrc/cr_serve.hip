@@ -1,13 +1,16 @@
 // Serving: continuous batching of convex-regression fits on one device.
 //
 // Requests enter a FIFO queue.  An admission step moves the head of the queue onto a free slot
-// as soon as one is free and the device bytes of its state (dominated by the two N^2 multiplier
-// buffers, plus the FP64 pair during a mixed-precision promotion) fit in the context's budget.
-// Each slot has its own worker thread and HIP stream, so admitted fits run concurrently on the
-// GPU and a new fit starts the moment one retires.  A fit's arithmetic does not depend on what
-// else is running (same kernels, tiling and fixed-order reductions), so its result is bitwise
-// the same alone and in a mix.  Strict FIFO: a head request that does not fit waits for memory
-// rather than being overtaken.
+// as soon as one is free and the device bytes of its state (its whole workspace, including the
+// FP64 copy a mixed-precision promotion would take) fit in the context's budget.  Each slot has
+// its own worker thread, HIP stream, pinned scalar buffer and device arena; a fit runs inside its
+// slot's arena (the solver's workspace mode), which grows to the largest fit the slot has run and
+// is then reused, so fits do not allocate or free device memory (hipFree would synchronize the
+// device under every other slot's work).  Admitted fits run concurrently on the GPU and a new fit
+// starts the moment one retires.  A fit's arithmetic does not depend on what else is running (same
+// kernels, tiling and fixed-order reductions), so its result is bitwise the same alone and in a
+// mix.  Strict FIFO: a head request that does not fit waits for memory rather than being
+// overtaken.
 
 #include "cr_internal.h"
 
@@ -42,6 +45,14 @@ struct Request {
     cr_report rep{};
 };
 
+// One slot's resources, created with the context and reused by every fit the slot runs.
+struct Slot {
+    hipStream_t stream = nullptr;
+    double *h_scal = nullptr;     // pinned, 32 doubles (trial scalars and the sequence word)
+    char *arena = nullptr;        // device workspace of the current capacity
+    size_t cap = 0;
+};
+
 }  // namespace
 
 struct cr_ctx {
@@ -51,18 +62,20 @@ struct cr_ctx {
     std::mutex mu;
     std::condition_variable cv_work;   // slot threads wait for assignments
     std::condition_variable cv_done;   // waiters for results / admission changes
+    std::condition_variable cv_idle;   // destroy waits for the callers inside cr_wait to leave
     std::deque<int64_t> queue;
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     std::vector<int64_t> assigned;     // per slot: request id or -1
     std::vector<std::thread> workers;
-    std::vector<hipStream_t> streams;
+    std::vector<Slot> slots;
     size_t resident = 0;
     int64_t next_id = 1;
     int64_t finished = 0, running = 0;
+    int waiters = 0;
     bool stop = false;
 
     void admit_locked() {
-        while (!queue.empty()) {
+        while (!stop && !queue.empty()) {
             Request *r = reqs[queue.front()].get();
             int slot = -1;
             for (int q = 0; q < max_slots; ++q)
@@ -82,10 +95,10 @@ struct cr_ctx {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             cv_work.wait(lk, [&] { return stop || assigned[slot] >= 0; });
-            if (stop) return;
+            if (assigned[slot] < 0) return;   // stopping and nothing assigned
             Request *r = reqs[assigned[slot]].get();
             lk.unlock();
-            run(r, streams[slot]);
+            run(r, slots[slot]);
             lk.lock();
             r->state = 2;
             resident -= r->bytes;
@@ -94,29 +107,64 @@ struct cr_ctx {
             ++finished;
             admit_locked();
             cv_done.notify_all();
+            if (stop) return;
         }
     }
 
-    void run(Request *r, hipStream_t st) {
+    // Grows the slot's arena to `need` bytes (freeing the smaller one first).
+    int reserve(Slot &sl, size_t need) {
+        if (need <= sl.cap) return CR_OK;
+        if (sl.arena) (void)hipFree(sl.arena);
+        sl.arena = nullptr;
+        sl.cap = 0;
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? CR_ENOMEM : CR_EDEVICE;
+        }
+        sl.arena = static_cast<char *>(p);
+        sl.cap = need;
+        return CR_OK;
+    }
+
+    void run(Request *r, Slot &sl) {
         cr_options o = r->opt;
         o.device = device;
-        o.stream = st;
+        o.stream = sl.stream;
         r->y.assign((size_t)r->N, 0.0);
         r->xi.assign((size_t)(r->N * r->n), 0.0);
-        r->status = cr_fit(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
-                           r->xi.data(), nullptr, &r->rep);
+        if (r->N == 1) {
+            r->status = cr_fit(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
+                               r->xi.data(), nullptr, &r->rep);
+        } else {
+            r->status = reserve(sl, r->bytes);
+            if (r->status == CR_OK) {
+                cr_workspace ws;
+                ws.base = sl.arena;
+                ws.size = sl.cap;
+                r->status = cr_fit_impl(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
+                                        r->xi.data(), nullptr, &r->rep, false, &ws, sl.h_scal);
+            }
+        }
         r->t_done = now_s();
         r->x.clear();
         r->x.shrink_to_fit();
     }
 };
 
+// Device bytes of one fit's whole state in a slot arena (0 for invalid arguments; N = 1 needs none).
+static size_t request_bytes(int64_t N, int64_t n, const cr_options &opt, int device) {
+    if (N == 1) return 0;
+    return cr_workspace_bytes(N, n, &opt, device, true);
+}
+
 extern "C" size_t cr_fit_state_bytes(int64_t N, int64_t n, int32_t precision) {
     if (N < 1 || n < 1 || n + 1 > 16 * cr::kMaxMB || precision < CR_FP64 || precision > CR_MIXED_BF16) return 0;
-    // the default (adaptive) step rule; it needs more than the constant step
-    size_t b = cr_state_bytes(N, n, precision, true);
-    if (precision != CR_FP64) b += cr_state_bytes(N, n, CR_FP64, true);   // promotion peak
-    return b;
+    cr_options o;
+    cr_default_options(&o);
+    o.precision = precision;
+    return request_bytes(N, n, o, 0);
 }
 
 extern "C" int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, cr_ctx **out) {
@@ -134,13 +182,19 @@ extern "C" int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, 
     }
     c->budget = byte_budget;
     c->assigned.assign((size_t)max_slots, -1);
-    c->streams.assign((size_t)max_slots, nullptr);
+    c->slots.resize((size_t)max_slots);
     for (int q = 0; q < max_slots; ++q) {
-        if (hipStreamCreateWithFlags(&c->streams[q], hipStreamNonBlocking) != hipSuccess) {
-            for (int p = 0; p < q; ++p) (void)hipStreamDestroy(c->streams[p]);
+        Slot &sl = c->slots[q];
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipHostMalloc((void **)&sl.h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            for (auto &o : c->slots) {
+                if (o.stream) (void)hipStreamDestroy(o.stream);
+                if (o.h_scal) (void)hipHostFree(o.h_scal);
+            }
             delete c;
             return CR_EDEVICE;
         }
+        std::memset(sl.h_scal, 0, 32 * sizeof(double));
     }
     for (int q = 0; q < max_slots; ++q) c->workers.emplace_back([c, q] { c->worker(q); });
     *out = c;
@@ -152,12 +206,32 @@ extern "C" int cr_ctx_destroy(cr_ctx *c) {
     {
         std::lock_guard<std::mutex> lk(c->mu);
         c->stop = true;
+        // queued requests are dropped: their waiters wake with CR_ECANCELED
+        for (int64_t id : c->queue) {
+            Request *r = c->reqs[id].get();
+            r->state = 2;
+            r->status = CR_ECANCELED;
+            r->t_done = now_s();
+        }
         c->queue.clear();
     }
     c->cv_work.notify_all();
+    c->cv_done.notify_all();
     // running fits finish their current solve before the threads exit
     for (auto &t : c->workers) t.join();
-    for (auto s : c->streams) (void)hipStreamDestroy(s);
+    {
+        // every request is done now; wait until the callers blocked in cr_wait have taken their
+        // results and left (they hold references into the context)
+        std::unique_lock<std::mutex> lk(c->mu);
+        c->cv_done.notify_all();
+        c->cv_idle.wait(lk, [&] { return c->waiters == 0; });
+    }
+    for (auto &sl : c->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.arena) (void)hipFree(sl.arena);
+        if (sl.h_scal) (void)hipHostFree(sl.h_scal);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
     delete c;
     return CR_OK;
 }
@@ -175,11 +249,11 @@ extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const
     r->tol = tol;
     if (opt) r->opt = *opt; else cr_default_options(&r->opt);
     if (r->opt.precision < CR_FP64 || r->opt.precision > CR_MIXED_BF16) return CR_EINVAL;
-    const bool adaptive = r->opt.step_rule != 0;
-    r->bytes = cr_state_bytes(N, n, r->opt.precision, adaptive);
-    if (r->opt.precision != CR_FP64) r->bytes += cr_state_bytes(N, n, CR_FP64, adaptive);   // promotion peak
+    r->bytes = request_bytes(N, n, r->opt, c->device);
+    if (N > 1 && r->bytes == 0) return CR_EINVAL;
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(c->mu);
+    if (c->stop) return CR_ECANCELED;
     if (r->bytes > c->budget) return CR_ENOMEM;
     r->id = c->next_id++;
     *req_id = r->id;
@@ -190,9 +264,11 @@ extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const
 }
 
 static int collect(cr_ctx *c, Request *r, int64_t id, double *y, double *xi, cr_report *rep, double *lat) {
-    if (y) std::memcpy(y, r->y.data(), r->y.size() * 8);
-    if (xi) std::memcpy(xi, r->xi.data(), r->xi.size() * 8);
-    if (rep) *rep = r->rep;
+    if (r->status != CR_ECANCELED) {
+        if (y) std::memcpy(y, r->y.data(), r->y.size() * 8);
+        if (xi) std::memcpy(xi, r->xi.data(), r->xi.size() * 8);
+        if (rep) *rep = r->rep;
+    }
     if (lat) *lat = r->t_done - r->t_submit;
     const int st = r->status;
     c->reqs.erase(id);
@@ -214,8 +290,11 @@ extern "C" int cr_wait(cr_ctx *c, int64_t id, double *y, double *xi, cr_report *
     auto it = c->reqs.find(id);
     if (it == c->reqs.end()) return CR_ENOTFOUND;
     Request *r = it->second.get();
+    ++c->waiters;
     c->cv_done.wait(lk, [&] { return r->state == 2; });
-    return collect(c, r, id, y, xi, rep, latency_s);
+    const int st = collect(c, r, id, y, xi, rep, latency_s);
+    if (--c->waiters == 0) c->cv_idle.notify_all();
+    return st;
 }
 
 extern "C" int cr_ctx_stats(cr_ctx *c, int64_t *queued, int64_t *running, int64_t *finished, size_t *resident) {

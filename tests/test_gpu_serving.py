@@ -90,3 +90,46 @@ def test_poll_and_stats(cr, torch_dev):
             time.sleep(0.001)
         assert got is not None
         assert srv.stats()["finished"] == 1
+
+
+def test_destroy_cancels_queued_requests(cr, torch_dev):
+    """Destroying a context with requests still queued: the running fit finishes, the queued ones are
+    dropped, and a caller blocked in cr_wait on one of them returns CR_ECANCELED (it is woken
+    before the context goes away)."""
+    import threading
+    reqs = [W.sq_norm(1000, 2, 0.1, 70 + r) for r in range(6)]
+    opt = cr.Options(precision="mixed_fp32", max_iters=3000)
+    srv = cr.Server(max_slots=1)
+    ids = [srv.submit(x, yb, 1e-3, 1e-9, opt) for (x, yb) in reqs]
+    got = {}
+
+    def waiter():
+        try:
+            srv.wait(ids[-1])
+            got["code"] = cr.CR_OK
+        except cr.CRError as e:
+            got["code"] = e.code
+    t = threading.Thread(target=waiter)
+    t.start()
+    time.sleep(0.3)
+    assert srv.stats()["queued"] >= 1
+    srv.close()
+    t.join(timeout=120)
+    assert not t.is_alive()
+    assert got["code"] == cr.CR_ECANCELED
+
+
+def test_slot_arenas_are_reused_across_sizes(cr, torch_dev):
+    """One slot runs fits of growing and shrinking size back to back in its arena (cleared between
+    fits): every result equals the fit run on its own."""
+    shapes = [(300, 4), (900, 12), (150, 2), (700, 30), (220, 7)]
+    reqs = [W.sq_norm(N, n, 0.1, 500 + k) for k, (N, n) in enumerate(shapes)]
+    opt = cr.Options(precision="mixed_fp32", max_iters=1500)
+    alone = [cr.fit(x, yb, 1e-3, 1e-4, opt) for (x, yb) in reqs]
+    with cr.Server(max_slots=1) as srv:
+        ids = [srv.submit(x, yb, 1e-3, 1e-4, opt) for (x, yb) in reqs]
+        served = [srv.wait(i) for i in ids]
+    for a, m in zip(alone, served):
+        np.testing.assert_array_equal(a.y, m.y)
+        np.testing.assert_array_equal(a.xi, m.xi)
+        assert a.report["iters"] == m.report["iters"]
