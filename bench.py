@@ -171,7 +171,7 @@ def cpu_baseline(x, ybar, delta: float, L: float, iters: int, rule: str, restart
 
 
 def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restart: bool,
-                rows_path: str | None = None) -> dict:
+                rows_path: str | None = None, group_max_n: int = 0) -> dict:
     """Replay a Poisson stream of fit requests through the continuous-batching context.
 
     Requests (N log-uniform in [100, 6000], n uniform in 2..32, ||x||^2 or 8-piece log-sum-exp,
@@ -183,7 +183,7 @@ def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restar
     reqs = W.serving_requests(count=count, seed=0)
     opt = cr.Options(precision=precision, step_rule=rule, restart=restart)
     ids = []
-    with cr.Server(max_slots=slots) as srv:
+    with cr.Server(max_slots=slots, group_max_n=group_max_n) as srv:
         t0 = time.perf_counter()
         for r in reqs:
             wait = r.arrival_s - (time.perf_counter() - t0)
@@ -192,6 +192,7 @@ def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restar
             ids.append(srv.submit(r.x, r.ybar, r.delta, r.tol, opt))
         res = [srv.wait(i) for i in ids]
         t_end = time.perf_counter() - t0
+        gs = srv.group_stats()
     lat = np.array([r.extra["latency_s"] for r in res])
     svc = np.array([r.report["seconds"] for r in res])
     wait_q = np.maximum(lat - svc, 0.0)
@@ -212,6 +213,8 @@ def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restar
             "p50_queue_s": pct(wait_q, 50), "p99_queue_s": pct(wait_q, 99),
             "p50_service_s": pct(svc, 50), "p99_service_s": pct(svc, 99),
             "busy_fit_s": round(float(svc.sum()), 2), "mean_iters": round(float(iters.mean()), 1),
+            "grouped_fit_rounds": int(gs["fit_rounds"]),
+            "fits_per_grouped_round": round(gs["fit_rounds"] / gs["rounds"], 2) if gs["rounds"] else None,
             "converged": conv, "arrival_span_s": round(reqs[-1].arrival_s, 3)}
 
 
@@ -350,6 +353,8 @@ def main() -> int:
                     help="also replay K requests of the serving stream (Poisson, 50/s) and report p50/p99 "
                          "latency and fits/s (0: skip)")
     ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
+    ap.add_argument("--group-max-n", type=int, default=0,
+                    help="serving: grouped iterations for fits with N <= this (0: per-slot launches)")
     ap.add_argument("--continuation", type=int, default=6, metavar="T",
                     help="also run T outer steps of the continuation to the unregularized estimator (0: skip)")
     ap.add_argument("--large", type=int, default=20000, metavar="K",
@@ -548,7 +553,7 @@ def main() -> int:
     }
     if args.serving > 0:
         out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision, rule, restart,
-                                     args.serving_rows)
+                                     args.serving_rows, args.group_max_n)
     if args.continuation > 0:
         out["continuation"] = run_continuation(cr, W, args.continuation, args.precision)
     if not args.no_configs:

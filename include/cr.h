@@ -327,6 +327,17 @@ size_t cr_fit_state_bytes(int64_t N, int64_t n, int32_t precision);
 /* Counters: fits queued, running, finished; bytes of multiplier state resident. */
 int cr_ctx_stats(cr_ctx *ctx, int64_t *queued, int64_t *running, int64_t *finished,
                  size_t *resident_bytes);
+/* Grouped iterations (off by default): fits admitted from now on with N <= max_n (0 = off) using
+ * the adaptive step hand each iteration's trial round (the pair sweep, its finalize, the step
+ * decision and the update) to the context's batcher, which launches the rounds of all such fits
+ * iterating at that moment as grouped kernels on one stream (one launch per kernel variant instead
+ * of one per fit).  Results are bitwise those of the fit run alone.  On one MI355X per-slot
+ * streams retire more fit iterations per second (the rounds of different fits overlap on the
+ * device; grouped rounds run in lockstep), hence the default. */
+int cr_ctx_set_grouping(cr_ctx *ctx, int64_t max_n);
+/* Counters of the grouped iterations: rounds launched, grouped pass launches, and the fit rounds
+ * they carried. */
+int cr_ctx_group_stats(cr_ctx *ctx, double *rounds, double *pass_launches, double *fit_rounds);
 
 #ifdef __cplusplus
 }

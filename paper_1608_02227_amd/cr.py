@@ -158,6 +158,8 @@ def load() -> C.CDLL:
         "cr_poll": (C.c_int, [vp, i64, vp, vp, _P(CRReport), _P(d)]),
         "cr_wait": (C.c_int, [vp, i64, vp, vp, _P(CRReport), _P(d)]),
         "cr_ctx_stats": (C.c_int, [vp, _P(i64), _P(i64), _P(i64), _P(C.c_size_t)]),
+        "cr_ctx_group_stats": (C.c_int, [vp, _P(d), _P(d), _P(d)]),
+        "cr_ctx_set_grouping": (C.c_int, [vp, i64]),
         "cr_fit_state_bytes": (C.c_size_t, [i64, i64, i32]),
     }
     for name, (res, args) in sig.items():
@@ -446,11 +448,17 @@ def state_bytes(N: int, n: int, precision: str = "fp64") -> int:
 class Server:
     """Continuous-batching fit server (cr_ctx_*): submit returns at once; wait/poll collect."""
 
-    def __init__(self, device: int = 0, byte_budget: int = 0, max_slots: int = 4):
+    def __init__(self, device: int = 0, byte_budget: int = 0, max_slots: int = 4, group_max_n: int = 0):
         h = C.c_void_p()
         _check(load().cr_ctx_create(device, byte_budget, max_slots, C.byref(h)), "cr_ctx_create")
         self._h = h
         self._shapes = {}
+        if group_max_n:
+            self.set_grouping(group_max_n)
+
+    def set_grouping(self, max_n: int):
+        """Grouped iterations for fits with N <= max_n admitted from now on (0: off)."""
+        _check(load().cr_ctx_set_grouping(self._h, max_n), "cr_ctx_set_grouping")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -497,3 +505,9 @@ class Server:
         q, r, f, b = C.c_int64(), C.c_int64(), C.c_int64(), C.c_size_t()
         _check(load().cr_ctx_stats(self._h, C.byref(q), C.byref(r), C.byref(f), C.byref(b)), "stats")
         return {"queued": q.value, "running": r.value, "finished": f.value, "resident_bytes": b.value}
+
+    def group_stats(self) -> dict:
+        """Grouped iterations so far: rounds launched, grouped pass launches, fit rounds carried."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(load().cr_ctx_group_stats(self._h, C.byref(a), C.byref(b), C.byref(c)), "group_stats")
+        return {"rounds": a.value, "pass_launches": b.value, "fit_rounds": c.value}

@@ -619,22 +619,7 @@ int cr_solver::step_adaptive() {
         } else {
             a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
         }
-        // the timed launches are the dominant kind: re-forming trials (split) or storing trials;
-        // one in four is sampled
-        const bool timed = ev_a && !ev_pending && (adv || !defer) && (timing_tick++ % 4 == 0);
-        if (timed) CR_HIP(hipEventRecord(ev_a, stream));
-        CR_HIP(launch_pass(g, adv ? PASS_ADV : (defer ? PASS_TRIAL_NS : PASS_TRIAL), fp32pass, rep, a, stream));
-        if (timed) {
-            CR_HIP(hipEventRecord(ev_b, stream));
-            ev_pending = true;
-            ev_pending_low = fp32pass;
-        }
-        if (adv) {
-            // lam^k now sits in lam[prv]: it becomes the current iterate
-            std::swap(cur, prv);
-            pend = false;
-            adv_passes += 1.0;
-        }
+        const PassMode mode = adv ? PASS_ADV : (defer ? PASS_TRIAL_NS : PASS_TRIAL);
         TrialFinalizeArgs f{};
         f.part_acc[0] = part_acc; f.part_acc[1] = part_acc2;
         f.part_col[0] = part_col; f.part_col[1] = part_col2;
@@ -645,7 +630,6 @@ int cr_solver::step_adaptive() {
         // h_scal (pinned host memory) receives ||A1^T D_a||^2, ||A2^T D_a||^2, the same for D_b,
         // ||D_a||^2, ||D_b||^2, <D_a, lam_a - lam^k>, <D_b, lam_b - lam^k>, then the decision
         // (candidate or -1 / -2, beta_k, t_{k+1}, restart)
-        CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
         const unsigned long long seq = ++trial_seq;
         // the reduction takes the step test's decision on the device (both candidates, the
         // restart, t_{k+1} and beta_k, in FP64; the host reads that decision back rather than
@@ -655,16 +639,55 @@ int cr_solver::step_adaptive() {
         // acceptance (split forms keep this trial's set for re-forming the candidate).
         const TrialRule rule{sa, sb, delta, t, opt.restart ? 1 : 0, opt.momentum ? 1 : 0};
         // without pinned host memory the scalars land in device memory and are copied back below
-        CR_HIP(launch_trial_reduce(g, block_part, part_red, h_pinned ? h_scal : trial_out,
-                                   h_pinned ? h_seq() : nullptr, seq, rule, decision, stream));
+        TrialReduceArgs red{};
+        red.block_part = block_part; red.nblk = g.Nr / 16;
+        red.part_red = part_red; red.nred = g.grid();
+        red.out = h_pinned ? h_scal : trial_out;
+        red.seq_out = h_pinned ? h_seq() : nullptr;
+        red.seq = seq;
+        red.rule = rule;
+        red.decision = decision;
+        AcceptArgs upd;
         {
             const int en = 1 - ecur;
             double *yn = defer ? yo64 : y64, *xin = defer ? xio64 : xi64, *dmyn = defer ? dmyo64 : dmy64;
             float *y32n = fp32pass ? (defer ? yo32 : y32) : nullptr;
             float *xi32n = fp32pass ? (defer ? xio32 : xi32) : nullptr;
             float *dmy32n = fp32pass ? (defer ? dmyo32 : dmy32) : nullptr;
-            CR_HIP(launch_accept(g, y64, xi64, yn, xin, dmyn, uD, wD, ye[ecur], xie[ecur], ye[en], xie[en], dmye[en],
-                                 y32n, xi32n, dmy32n, xhat64, 1.0 / delta, 0.0, decision, stream));
+            upd = make_accept_args(g, y64, xi64, yn, xin, dmyn, uD, wD, ye[ecur], xie[ecur], ye[en], xie[en],
+                                   dmye[en], y32n, xi32n, dmy32n, xhat64, 1.0 / delta, 0.0, decision);
+        }
+        if (batch && h_pinned) {
+            // grouped with the other fits iterating now (serving); ordered behind this stream's
+            // work by ev_ready, and this stream's later work behind the round by plan.done
+            TrialPlan plan;
+            plan.g = g; plan.mode = mode; plan.fp32 = fp32pass; plan.rep = rep;
+            plan.pass = a; plan.fin = f; plan.red = red; plan.acc = upd;
+            plan.ready = ev_ready;
+            CR_HIP(hipEventRecord(ev_ready, stream));
+            const int rc = cr_batcher_run(batch, &plan);
+            if (rc) return rc;
+            CR_HIP(hipStreamWaitEvent(stream, plan.done, 0));
+        } else {
+            // the timed launches are the dominant kind: re-forming trials (split) or storing
+            // trials; one in four is sampled
+            const bool timed = ev_a && !ev_pending && (adv || !defer) && (timing_tick++ % 4 == 0);
+            if (timed) CR_HIP(hipEventRecord(ev_a, stream));
+            CR_HIP(launch_pass(g, mode, fp32pass, rep, a, stream));
+            if (timed) {
+                CR_HIP(hipEventRecord(ev_b, stream));
+                ev_pending = true;
+                ev_pending_low = fp32pass;
+            }
+            CR_HIP(launch_trial_finalize(g, fp32pass, f, stream));
+            CR_HIP(launch_trial_reduce(g, block_part, part_red, red.out, red.seq_out, seq, rule, decision, stream));
+            CR_HIP(launch_accept_args(g, upd, stream));
+        }
+        if (adv) {
+            // lam^k now sits in lam[prv]: it becomes the current iterate
+            std::swap(cur, prv);
+            pend = false;
+            adv_passes += 1.0;
         }
         if (h_pinned) {
             const int rc = wait_trial(seq);
@@ -1004,6 +1027,16 @@ int cr_solver::promote() {
     return CR_OK;
 }
 
+namespace {
+// Counts a fit as iterating for its batcher (if any) while in scope: the batcher's rounds wait
+// for the fits that are iterating, not for those in a stopping test.
+struct Iterating {
+    cr_batcher *b;
+    explicit Iterating(cr_batcher *b_) : b(b_) { if (b) cr_batcher_active(b, +1); }
+    ~Iterating() { if (b) cr_batcher_active(b, -1); }
+};
+}  // namespace
+
 int cr_solver::solve(double tol, cr_report *rep_out) {
     const double t0 = now_s();
     CR_HIP(hipSetDevice(device));
@@ -1029,6 +1062,11 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
         // (max ybar - min ybar) / scale: when that exceeds tol the test cannot pass and is skipped.
         if (k == 0 && lam_zero && !by_gap && yrange / scale > tol && kmax > 0) {
             int rc = CR_OK;
+            if (adaptive && batch && !primed) {
+                rc = prime();   // outside the batcher's rounds: the first step would prime itself
+                if (rc) return rc;
+            }
+            const Iterating it(adaptive ? batch : nullptr);
             for (int64_t q = 0; q < std::min<int64_t>(opt.check_every, kmax); ++q) {
                 rc = adaptive ? step_adaptive() : step_once();
                 if (rc) break;
@@ -1079,6 +1117,11 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
             prev_k = k;
         }
         const int64_t todo = std::min<int64_t>(gap, kmax - k);
+        if (adaptive && batch && !primed) {
+            rc = prime();
+            if (rc) return rc;
+        }
+        const Iterating it(adaptive && todo > 0 ? batch : nullptr);
         for (int64_t q = 0; q < todo; ++q) {
             rc = adaptive ? step_adaptive() : step_once();
             if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
@@ -1263,7 +1306,7 @@ static int fit_trivial(int64_t N, int64_t n, const double *ybar, double *y, doub
 
 int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
                 const cr_options *opt_in, double *y, double *xi, double *lambda, cr_report *rep, bool dev,
-                cr_workspace *ws, double *pinned_scal) {
+                cr_workspace *ws, double *pinned_scal, cr_batcher *batch, hipEvent_t ev_ready) {
     const double t0 = now_s();
     cr_options opt;
     if (opt_in) opt = *opt_in; else cr_default_options(&opt);
@@ -1275,6 +1318,10 @@ int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, doubl
     cr_solver *s = nullptr;
     rc = cr_solver_create_impl(N, n, x, ybar, delta, &opt, nullptr, dev, &s, ws, pinned_scal);
     if (rc) return rc;
+    if (batch && ev_ready && s->h_pinned) {
+        s->batch = batch;
+        s->ev_ready = ev_ready;
+    }
     if (opt.L > 0.0) { s->L = opt.L; s->s_step = opt.L; }
     cr_report r;
     int status = s->solve(tol, &r);

@@ -16,6 +16,36 @@ struct cr_workspace {
     bool counting = false;
 };
 
+struct cr_batcher;
+
+// One fit's trial round (pass, finalize, reduction with the step decision, queued update) handed
+// to a cr_batcher, which launches the rounds of all fits waiting at that moment grouped.
+struct TrialPlan {
+    cr::Geometry g{};
+    cr::PassMode mode = cr::PASS_TRIAL;
+    bool fp32 = false;
+    cr::LamRep rep = cr::REP_F64;
+    cr::PassArgs pass{};
+    cr::TrialFinalizeArgs fin{};
+    cr::TrialReduceArgs red{};
+    cr::AcceptArgs acc{};
+    hipEvent_t ready = nullptr;   // recorded on the fit's stream behind the work the round reads
+    hipEvent_t done = nullptr;    // set by the batcher: recorded behind the round's launches
+    alignas(4) int launched_flag = 0;   // set (atomically) once the round is launched
+    int status = CR_OK;
+};
+
+// Groups the adaptive step's trial rounds of several fits (serving): the rounds of the fits
+// currently iterating are gathered and launched as grouped kernels on the batcher's stream.
+cr_batcher *cr_batcher_create(int device);
+void cr_batcher_destroy(cr_batcher *b);
+// Blocks until the plan's round has been launched; then plan->done orders the fit's next work.
+int cr_batcher_run(cr_batcher *b, TrialPlan *plan);
+// A fit enters (+1) or leaves (-1) its iterations: a round waits (briefly) for every active fit.
+void cr_batcher_active(cr_batcher *b, int delta);
+// Rounds, grouped pass launches and fit rounds launched so far.
+void cr_batcher_stats(cr_batcher *b, double *rounds, double *pass_launches, double *fit_rounds);
+
 struct cr_solver {
     cr::Geometry g{};
     int device = -1;
@@ -92,6 +122,10 @@ struct cr_solver {
     double *in_x = nullptr, *in_y = nullptr, *in_mu = nullptr;   // input staging (set-up only)
     double h_local[32] = {};
     double *trial_out = nullptr;    // device copy of the trial scalars when h_scal is not pinned
+    // grouped trial rounds (serving): the adaptive step hands its rounds to `batch` (needs pinned
+    // h_scal); ev_ready orders them behind this fit's stream
+    cr_batcher *batch = nullptr;
+    hipEvent_t ev_ready = nullptr;
 
     // iteration state
     double L = 0.0, sigma2 = 0.0, preprocess_s = 0.0;
@@ -145,9 +179,12 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
 // takes if it promotes; 0 if the arguments are invalid.
 size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt, int device, bool promotion = false);
 // One complete fit (the body of cr_fit / cr_fit_device), optionally inside a workspace.
+// batch/ev_ready (optional): group the adaptive step's trial rounds through `batch`, ordering
+// them behind the fit's stream with the caller's event ev_ready.
 int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
                 const cr_options *opt, double *y, double *xi, double *lambda, cr_report *rep, bool dev,
-                cr_workspace *ws = nullptr, double *pinned_scal = nullptr);
+                cr_workspace *ws = nullptr, double *pinned_scal = nullptr, cr_batcher *batch = nullptr,
+                hipEvent_t ev_ready = nullptr);
 size_t cr_state_bytes(int64_t N, int64_t n, int precision, bool adaptive);
 
 namespace cr {

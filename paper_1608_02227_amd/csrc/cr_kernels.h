@@ -186,6 +186,75 @@ hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit,
                          double *ye, double *xie, double *dmye, float *y32, float *xi32, float *dmy32,
                          const double *xhat64, double inv_delta, double beta, const double *decision, hipStream_t st);
 
+// ---- grouped launches (serving: the same step of several small fits in one launch) ----------
+// Fit f of a group owns the launch's workgroups [off[f], off[f + 1]); its tiles, reductions and
+// outputs are exactly those of its own launch, so results are bitwise the same grouped or alone.
+// The descriptors travel as kernel arguments (no device memory), kGroupMax fits per launch.
+constexpr int kGroupMax = 8;
+
+struct PassGroup {
+    int nfit;
+    int off[kGroupMax + 1];
+    Geometry g[kGroupMax];
+    PassArgs a[kGroupMax];
+};
+// Fits can share a grouped pass when these agree: mode, arithmetic, representation, feature
+// blocks and the residual K-step trim (the kernel's template parameters).
+int pass_group_key(const Geometry &g, PassMode mode, bool fp32, LamRep rep);
+hipError_t launch_pass_group(PassMode mode, bool fp32, LamRep rep, const PassGroup &G, hipStream_t st);
+
+struct TrialFinalizeGroup {
+    int nfit;
+    int off[kGroupMax + 1];
+    Geometry g[kGroupMax];
+    TrialFinalizeArgs a[kGroupMax];
+};
+// All fits of the group share fp32 and MB.
+hipError_t launch_trial_finalize_group(bool fp32, int MB, const TrialFinalizeGroup &G, hipStream_t st);
+
+struct TrialReduceArgs {
+    const double *block_part;
+    int nblk;                 // Nr / 16
+    const double *part_red;
+    int nred;                 // the pass's workgroup count
+    double *out;
+    unsigned long long *seq_out;
+    unsigned long long seq;
+    TrialRule rule;
+    double *decision;
+};
+struct TrialReduceGroup {
+    int nfit;
+    TrialReduceArgs a[kGroupMax];
+};
+hipError_t launch_trial_reduce_group(const TrialReduceGroup &G, hipStream_t st);
+
+// The arguments of launch_accept (see there).
+struct AcceptArgs {
+    const double *yt, *xit;
+    double *y, *xi, *dmy;
+    const double *uD0, *uD1, *wD0, *wD1;
+    const double *yk, *xik;
+    double *ye, *xie, *dmye;
+    float *y32, *xi32, *dmy32;
+    const double *xhat64;
+    double inv_delta, beta;
+    const double *decision;
+    int N, n, NP;
+};
+struct AcceptGroup {
+    int nfit;
+    int off[kGroupMax + 1];
+    AcceptArgs a[kGroupMax];
+};
+hipError_t launch_accept_group(const AcceptGroup &G, hipStream_t st);
+hipError_t launch_accept_args(const Geometry &g, const AcceptArgs &a, hipStream_t st);
+AcceptArgs make_accept_args(const Geometry &g, const double *yt, const double *xit, double *y, double *xi,
+                            double *dmy, const double *const uD[2], const double *const wD[2], const double *yk,
+                            const double *xik, double *ye, double *xie, double *dmye, float *y32, float *xi32,
+                            float *dmy32, const double *xhat64, double inv_delta, double beta,
+                            const double *decision);
+
 // Sums / maxima of per-block partials: out[q] = op_q over blocks of part[b * stride + q],
 // with op = max for q < nmax and sum otherwise.  Single workgroup, deterministic order.
 hipError_t launch_reduce(const double *part, int blocks, int stride, int nmax, int nout,

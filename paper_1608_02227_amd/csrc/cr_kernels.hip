@@ -139,8 +139,10 @@ template <typename T> __device__ __forceinline__ T row16_sum(T v) {
 // ---- the pair sweep -----------------------------------------------------------------------
 // KT: residual K-steps dropped at the end (4 MB - KT steps of 4 features); the launcher passes
 // KT > 0 only when every dropped step lies beyond feature n - 1, where Xi is zero.
-template <typename T, int REP, int MODE, int MB, int KT = 0>
-__global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry g) {
+// `bid` is the workgroup's index within the fit's own grid (blockIdx.x for a single fit; the
+// grouped launch below maps its workgroups onto several fits).
+template <typename T, int REP, int MODE, int MB, int KT>
+__device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, const int bid) {
     constexpr int NP = 16 * MB;
     constexpr int KS = 4 * MB - KT;                  // residual K-steps
     static_assert(KT >= 0 && KS >= 1, "at least one residual step");
@@ -193,8 +195,8 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
 
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, lr = l & 15, lq = l >> 4;
-    const int chunk = blockIdx.x % g.chunks;        // consecutive workgroups: one chunk per XCD
-    const int strip = blockIdx.x / g.chunks;
+    const int chunk = bid % g.chunks;               // consecutive workgroups: one chunk per XCD
+    const int strip = bid / g.chunks;
     const int i = strip * kRows + w * 16 + lr;      // < Nr always
     const bool row_ok = i < g.N;
     const int cbeg = chunk * g.chunk_cols;
@@ -710,9 +712,24 @@ __global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry 
                 else if (MODE == PASS_POWER && tid == 1) v = fmax(v, o);
                 else v += o;
             }
-            a.part_red[(size_t)blockIdx.x * kRed + tid] = v;
+            a.part_red[(size_t)bid * kRed + tid] = v;
         }
     }
+}
+
+template <typename T, int REP, int MODE, int MB, int KT = 0>
+__global__ __launch_bounds__(64 * kWaves) void pass_kernel(PassArgs a, Geometry g) {
+    pass_body<T, REP, MODE, MB, KT>(a, g, blockIdx.x);
+}
+
+// Grouped pass: the workgroups of several fits (same template parameters) in one launch; fit f
+// owns workgroups [off[f], off[f + 1]).  Each fit's tiles, reductions and outputs are those of its
+// own launch, so its results are bitwise the same grouped or alone.
+template <typename T, int REP, int MODE, int MB, int KT = 0>
+__global__ __launch_bounds__(64 * kWaves) void pass_group_kernel(PassGroup G) {
+    int f = 0;
+    while (f + 1 < G.nfit && (int)blockIdx.x >= G.off[f + 1]) ++f;
+    pass_body<T, REP, MODE, MB, KT>(G.a[f], G.g[f], (int)blockIdx.x - G.off[f]);
 }
 
 static int env_int(const char *name, int def) {
@@ -824,6 +841,56 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, 
         return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
+}
+
+int pass_group_key(const Geometry &g, PassMode mode, bool fp32, LamRep rep) {
+    constexpr int kHotTrim = 2;
+    const bool hot = (mode == PASS_STEP || mode == PASS_TRIAL || mode == PASS_TRIAL_NS || mode == PASS_ADV);
+    const int kt = (hot && 4 * g.MB - g.ks1 >= kHotTrim) ? kHotTrim : 0;
+    return (((int)mode * 2 + (fp32 ? 1 : 0)) * 4 + (int)rep) * 64 + g.MB * 8 + kt;
+}
+
+template <typename T, int REP, int MODE, int KT>
+static void launch_group_kt(const PassGroup &G, int MB, hipStream_t st) {
+    dim3 grid(G.off[G.nfit]), block(64 * kWaves);
+    switch (MB) {
+    case 1: hipLaunchKernelGGL((pass_group_kernel<T, REP, MODE, 1, KT>), grid, block, 0, st, G); break;
+    case 2: hipLaunchKernelGGL((pass_group_kernel<T, REP, MODE, 2, KT>), grid, block, 0, st, G); break;
+    case 3: hipLaunchKernelGGL((pass_group_kernel<T, REP, MODE, 3, KT>), grid, block, 0, st, G); break;
+    default: hipLaunchKernelGGL((pass_group_kernel<T, REP, MODE, 4, KT>), grid, block, 0, st, G); break;
+    }
+}
+
+template <typename T, int REP, int MODE>
+static hipError_t launch_group_mb(const PassGroup &G, hipStream_t st) {
+    const Geometry &g = G.g[0];
+    if (g.MB < 1 || g.MB > kMaxMB) return hipErrorInvalidValue;
+    if (4 * g.MB - g.ks1 >= 2) launch_group_kt<T, REP, MODE, 2>(G, g.MB, st);
+    else launch_group_kt<T, REP, MODE, 0>(G, g.MB, st);
+    return hipGetLastError();
+}
+
+// The grouped forms of the per-iteration trial passes (the adaptive step's sweeps).
+hipError_t launch_pass_group(PassMode mode, bool fp32, LamRep rep, const PassGroup &G, hipStream_t st) {
+    if (G.nfit < 1 || G.nfit > kGroupMax) return hipErrorInvalidValue;
+    const int key = pass_group_key(G.g[0], mode, fp32, rep);
+    for (int f = 1; f < G.nfit; ++f)
+        if (pass_group_key(G.g[f], mode, fp32, rep) != key) return hipErrorInvalidValue;
+    switch (mode) {
+    case PASS_TRIAL:
+        if (!fp32 && rep == REP_F64) return launch_group_mb<double, REP_F64, PASS_TRIAL>(G, st);
+        return hipErrorInvalidValue;
+    case PASS_TRIAL_NS:
+        if (fp32 && rep == REP_SPLIT_F32) return launch_group_mb<float, REP_SPLIT_F32, PASS_TRIAL_NS>(G, st);
+        if (fp32 && rep == REP_SPLIT_BF16) return launch_group_mb<float, REP_SPLIT_BF16, PASS_TRIAL_NS>(G, st);
+        return hipErrorInvalidValue;
+    case PASS_ADV:
+        if (fp32 && rep == REP_SPLIT_F32) return launch_group_mb<float, REP_SPLIT_F32, PASS_ADV>(G, st);
+        if (fp32 && rep == REP_SPLIT_BF16) return launch_group_mb<float, REP_SPLIT_BF16, PASS_ADV>(G, st);
+        return hipErrorInvalidValue;
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 // ---- finalize: partial sums -> primal point ------------------------------------------------
@@ -1298,33 +1365,29 @@ hipError_t launch_lincomb(const Geometry &g, const double *ya, const double *xia
 // With `decision` set, the candidate (0 or 1; negative: none, the kernel does nothing) and beta
 // are read from decision[0], decision[1] as the trial reduction left them, and uD / wD point at
 // the two candidates' adjoints; otherwise candidate 0 and the `beta` argument are used.
-__global__ __launch_bounds__(256) void accept_kernel(const double *yt, const double *xit, double *y, double *xi,
-                                                    double *dmy, const double *uD0, const double *uD1,
-                                                    const double *wD0, const double *wD1, const double *yk,
-                                                    const double *xik, double *ye, double *xie, double *dmye,
-                                                    float *y32, float *xi32, float *dmy32, const double *xhat64,
-                                                    double inv_delta, double beta, const double *decision,
-                                                    int N, int n, int NP) {
-    const double *uD = uD0, *wD = wD0;
-    if (decision) {
-        const double acc = decision[0];
+__device__ __forceinline__ void accept_body(const AcceptArgs &a, const int bid) {
+    const double *uD = a.uD0, *wD = a.wD0;
+    double beta = a.beta;
+    if (a.decision) {
+        const double acc = a.decision[0];
         if (acc < 0.0) return;
-        beta = decision[1];
-        if (acc > 0.5) { uD = uD1; wD = wD1; }
+        beta = a.decision[1];
+        if (acc > 0.5) { uD = a.uD1; wD = a.wD1; }
     }
+    const int NP = a.NP;
     const int t = threadIdx.x & 15;
-    const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int i = bid * 16 + (threadIdx.x >> 4);
     double dn = 0.0, dp = 0.0;
     for (int m = t; m < NP; m += 16) {
         const size_t e = (size_t)i * NP + m;
-        const double xn = xit[e] + wD[e] * inv_delta;
-        const double xp = (1.0 + beta) * xn - beta * xik[e];
-        xie[e] = xn;
-        xi[e] = xp;
-        if (xi32) xi32[e] = (float)xp;
-        if (m < n) {
-            dn += xn * xhat64[e];
-            dp += xp * xhat64[e];
+        const double xn = a.xit[e] + wD[e] * a.inv_delta;
+        const double xp = (1.0 + beta) * xn - beta * a.xik[e];
+        a.xie[e] = xn;
+        a.xi[e] = xp;
+        if (a.xi32) a.xi32[e] = (float)xp;
+        if (m < a.n) {
+            dn += xn * a.xhat64[e];
+            dp += xp * a.xhat64[e];
         }
     }
     for (int s = 1; s < 16; s <<= 1) {
@@ -1332,25 +1395,59 @@ __global__ __launch_bounds__(256) void accept_kernel(const double *yt, const dou
         dp += __shfl_xor(dp, s, 16);
     }
     if (t == 0) {
-        const bool valid = i < N;
-        const double yn = yt[i] + uD[i];
-        const double yp = (1.0 + beta) * yn - beta * yk[i];
-        ye[i] = yn;
-        dmye[i] = valid ? dn - yn : 0.0;
-        y[i] = yp;
-        dmy[i] = valid ? dp - yp : 0.0;
-        if (y32) y32[i] = (float)yp;
-        if (dmy32) dmy32[i] = valid ? (float)(dp - yp) : 0.f;
+        const bool valid = i < a.N;
+        const double yn = a.yt[i] + uD[i];
+        const double yp = (1.0 + beta) * yn - beta * a.yk[i];
+        a.ye[i] = yn;
+        a.dmye[i] = valid ? dn - yn : 0.0;
+        a.y[i] = yp;
+        a.dmy[i] = valid ? dp - yp : 0.0;
+        if (a.y32) a.y32[i] = (float)yp;
+        if (a.dmy32) a.dmy32[i] = valid ? (float)(dp - yp) : 0.f;
     }
+}
+
+__global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) { accept_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void accept_group_kernel(AcceptGroup G) {
+    int f = 0;
+    while (f + 1 < G.nfit && (int)blockIdx.x >= G.off[f + 1]) ++f;
+    accept_body(G.a[f], (int)blockIdx.x - G.off[f]);
+}
+
+AcceptArgs make_accept_args(const Geometry &g, const double *yt, const double *xit, double *y, double *xi,
+                            double *dmy, const double *const uD[2], const double *const wD[2], const double *yk,
+                            const double *xik, double *ye, double *xie, double *dmye, float *y32, float *xi32,
+                            float *dmy32, const double *xhat64, double inv_delta, double beta,
+                            const double *decision) {
+    AcceptArgs a;
+    a.yt = yt; a.xit = xit; a.y = y; a.xi = xi; a.dmy = dmy;
+    a.uD0 = uD[0]; a.uD1 = uD[1]; a.wD0 = wD[0]; a.wD1 = wD[1];
+    a.yk = yk; a.xik = xik; a.ye = ye; a.xie = xie; a.dmye = dmye;
+    a.y32 = y32; a.xi32 = xi32; a.dmy32 = dmy32; a.xhat64 = xhat64;
+    a.inv_delta = inv_delta; a.beta = beta; a.decision = decision;
+    a.N = g.N; a.n = g.n; a.NP = g.NP;
+    return a;
 }
 
 hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit, double *y, double *xi, double *dmy,
                          const double *const uD[2], const double *const wD[2], const double *yk, const double *xik,
                          double *ye, double *xie, double *dmye, float *y32, float *xi32, float *dmy32,
                          const double *xhat64, double inv_delta, double beta, const double *decision, hipStream_t st) {
-    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, yt, xit, y, xi, dmy, uD[0], uD[1], wD[0],
-                       wD[1], yk, xik, ye, xie, dmye, y32, xi32, dmy32, xhat64, inv_delta, beta, decision, g.N, g.n,
-                       g.NP);
+    const AcceptArgs a = make_accept_args(g, yt, xit, y, xi, dmy, uD, wD, yk, xik, ye, xie, dmye, y32, xi32, dmy32,
+                                          xhat64, inv_delta, beta, decision);
+    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_args(const Geometry &g, const AcceptArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(accept_kernel, dim3(g.Nr / 16), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_group(const AcceptGroup &G, hipStream_t st) {
+    if (G.nfit < 1 || G.nfit > kGroupMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(accept_group_kernel, dim3(G.off[G.nfit]), dim3(256), 0, st, G);
     return hipGetLastError();
 }
 
@@ -1358,12 +1455,12 @@ hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit,
 // power-mode finalize, plus per-block sums of ||A1^T D_q||^2 and ||A2^T D_q||^2 (4 per block).
 // The two candidates run in the two halves of the workgroup (threads 0-255 and 256-511).
 template <typename T, int MB>
-__global__ __launch_bounds__(512) void trial_finalize_kernel(TrialFinalizeArgs a, Geometry g) {
+__device__ __forceinline__ void trial_finalize_body(const TrialFinalizeArgs &a, const Geometry &g, const int bid) {
     constexpr int NP = 16 * MB;
     const int q = threadIdx.x >> 8;
     const int t = threadIdx.x & 15;
     const int r = (threadIdx.x & 255) >> 4;
-    const int i = blockIdx.x * 16 + r;
+    const int i = bid * 16 + r;
     const bool valid = i < g.N;
     __shared__ double sh[16][4];
     {
@@ -1406,8 +1503,37 @@ __global__ __launch_bounds__(512) void trial_finalize_kernel(TrialFinalizeArgs a
     if (threadIdx.x < 4) {
         double s = 0.0;
         for (int rr = 0; rr < 16; ++rr) s += sh[rr][threadIdx.x];
-        a.block_part[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
+        a.block_part[(size_t)bid * 4 + threadIdx.x] = s;
     }
+}
+
+template <typename T, int MB>
+__global__ __launch_bounds__(512) void trial_finalize_kernel(TrialFinalizeArgs a, Geometry g) {
+    trial_finalize_body<T, MB>(a, g, blockIdx.x);
+}
+
+template <typename T, int MB>
+__global__ __launch_bounds__(512) void trial_finalize_group_kernel(TrialFinalizeGroup G) {
+    int f = 0;
+    while (f + 1 < G.nfit && (int)blockIdx.x >= G.off[f + 1]) ++f;
+    trial_finalize_body<T, MB>(G.a[f], G.g[f], (int)blockIdx.x - G.off[f]);
+}
+
+hipError_t launch_trial_finalize_group(bool fp32, int MB, const TrialFinalizeGroup &G, hipStream_t st) {
+    if (G.nfit < 1 || G.nfit > kGroupMax) return hipErrorInvalidValue;
+    dim3 grid(G.off[G.nfit]), block(512);
+#define CR_TFING(T, MBV) hipLaunchKernelGGL((trial_finalize_group_kernel<T, MBV>), grid, block, 0, st, G)
+    if (fp32) {
+        switch (MB) { case 1: CR_TFING(float, 1); break; case 2: CR_TFING(float, 2); break;
+                      case 3: CR_TFING(float, 3); break; case 4: CR_TFING(float, 4); break;
+                      default: return hipErrorInvalidValue; }
+    } else {
+        switch (MB) { case 1: CR_TFING(double, 1); break; case 2: CR_TFING(double, 2); break;
+                      case 3: CR_TFING(double, 3); break; case 4: CR_TFING(double, 4); break;
+                      default: return hipErrorInvalidValue; }
+    }
+#undef CR_TFING
+    return hipGetLastError();
 }
 
 hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinalizeArgs &a, hipStream_t st) {
@@ -1436,10 +1562,9 @@ hipError_t launch_trial_finalize(const Geometry &g, bool fp32, const TrialFinali
 // -2 (a non-finite scalar); decision[1] = beta_k, decision[2] = t_{k+1}, decision[3] = 1 if the
 // momentum restarts (restart on and <D, candidate - lam^k> < 0).  The same four values follow the
 // eight scalars in out[8..11].
-__global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int ba, const double *pb, int bb,
-                                                          double *out, unsigned long long *seq_out,
-                                                          unsigned long long seq, TrialRule rule,
-                                                          double *decision) {
+__device__ __forceinline__ void trial_reduce_body(const double *pa, int ba, const double *pb, int bb, double *out,
+                                                  unsigned long long *seq_out, unsigned long long seq,
+                                                  const TrialRule &rule, double *decision) {
     __shared__ double sh[8][256];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1486,6 +1611,25 @@ __global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int
             *reinterpret_cast<volatile unsigned long long *>(seq_out) = seq;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void trial_reduce_kernel(const double *pa, int ba, const double *pb, int bb,
+                                                          double *out, unsigned long long *seq_out,
+                                                          unsigned long long seq, TrialRule rule,
+                                                          double *decision) {
+    trial_reduce_body(pa, ba, pb, bb, out, seq_out, seq, rule, decision);
+}
+
+// one workgroup per fit
+__global__ __launch_bounds__(256) void trial_reduce_group_kernel(TrialReduceGroup G) {
+    const TrialReduceArgs &a = G.a[blockIdx.x];
+    trial_reduce_body(a.block_part, a.nblk, a.part_red, a.nred, a.out, a.seq_out, a.seq, a.rule, a.decision);
+}
+
+hipError_t launch_trial_reduce_group(const TrialReduceGroup &G, hipStream_t st) {
+    if (G.nfit < 1 || G.nfit > kGroupMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(trial_reduce_group_kernel, dim3(G.nfit), dim3(256), 0, st, G);
+    return hipGetLastError();
 }
 
 hipError_t launch_trial_reduce(const Geometry &g, const double *block_part, const double *part_red, double *out,

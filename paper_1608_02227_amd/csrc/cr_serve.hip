@@ -48,10 +48,13 @@ struct Request {
 // One slot's resources, created with the context and reused by every fit the slot runs.
 struct Slot {
     hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr;   // orders the slot's grouped trial rounds behind its stream
     double *h_scal = nullptr;     // pinned, 32 doubles (trial scalars and the sequence word)
     char *arena = nullptr;        // device workspace of the current capacity
     size_t cap = 0;
 };
+
+
 
 }  // namespace
 
@@ -73,6 +76,10 @@ struct cr_ctx {
     int64_t finished = 0, running = 0;
     int waiters = 0;
     bool stop = false;
+    // grouped iterations (cr_ctx_set_grouping): fits with N <= group_max_n hand their adaptive-step
+    // rounds to `batch`; off (0) by default
+    cr_batcher *batch = nullptr;
+    int64_t group_max_n = 0;
 
     void admit_locked() {
         while (!stop && !queue.empty()) {
@@ -97,8 +104,9 @@ struct cr_ctx {
             cv_work.wait(lk, [&] { return stop || assigned[slot] >= 0; });
             if (assigned[slot] < 0) return;   // stopping and nothing assigned
             Request *r = reqs[assigned[slot]].get();
+            cr_batcher *b = (batch && r->N <= group_max_n && r->opt.step_rule == 1) ? batch : nullptr;
             lk.unlock();
-            run(r, slots[slot]);
+            run(r, slots[slot], b);
             lk.lock();
             r->state = 2;
             resident -= r->bytes;
@@ -128,7 +136,7 @@ struct cr_ctx {
         return CR_OK;
     }
 
-    void run(Request *r, Slot &sl) {
+    void run(Request *r, Slot &sl, cr_batcher *b) {
         cr_options o = r->opt;
         o.device = device;
         o.stream = sl.stream;
@@ -144,7 +152,8 @@ struct cr_ctx {
                 ws.base = sl.arena;
                 ws.size = sl.cap;
                 r->status = cr_fit_impl(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
-                                        r->xi.data(), nullptr, &r->rep, false, &ws, sl.h_scal);
+                                        r->xi.data(), nullptr, &r->rep, false, &ws, sl.h_scal, b,
+                                        b ? sl.ready : nullptr);
             }
         }
         r->t_done = now_s();
@@ -183,18 +192,23 @@ extern "C" int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, 
     c->budget = byte_budget;
     c->assigned.assign((size_t)max_slots, -1);
     c->slots.resize((size_t)max_slots);
-    for (int q = 0; q < max_slots; ++q) {
+    bool ok = true;
+    for (int q = 0; ok && q < max_slots; ++q) {
         Slot &sl = c->slots[q];
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipHostMalloc((void **)&sl.h_scal, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-            for (auto &o : c->slots) {
-                if (o.stream) (void)hipStreamDestroy(o.stream);
-                if (o.h_scal) (void)hipHostFree(o.h_scal);
-            }
-            delete c;
-            return CR_EDEVICE;
+        ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc((void **)&sl.h_scal, 32 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+        if (ok) std::memset(sl.h_scal, 0, 32 * sizeof(double));
+    }
+    if (!ok) {
+        for (auto &o : c->slots) {
+            if (o.stream) (void)hipStreamDestroy(o.stream);
+            if (o.ready) (void)hipEventDestroy(o.ready);
+            if (o.h_scal) (void)hipHostFree(o.h_scal);
         }
-        std::memset(sl.h_scal, 0, 32 * sizeof(double));
+        cr_batcher_destroy(c->batch);
+        delete c;
+        return CR_EDEVICE;
     }
     for (int q = 0; q < max_slots; ++q) c->workers.emplace_back([c, q] { c->worker(q); });
     *out = c;
@@ -226,10 +240,12 @@ extern "C" int cr_ctx_destroy(cr_ctx *c) {
         c->cv_done.notify_all();
         c->cv_idle.wait(lk, [&] { return c->waiters == 0; });
     }
+    cr_batcher_destroy(c->batch);   // no fit is running: its thread has nothing left to launch
     for (auto &sl : c->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.arena) (void)hipFree(sl.arena);
         if (sl.h_scal) (void)hipHostFree(sl.h_scal);
+        if (sl.ready) (void)hipEventDestroy(sl.ready);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete c;
@@ -304,5 +320,25 @@ extern "C" int cr_ctx_stats(cr_ctx *c, int64_t *queued, int64_t *running, int64_
     if (running) *running = c->running;
     if (finished) *finished = c->finished;
     if (resident) *resident = c->resident;
+    return CR_OK;
+}
+
+extern "C" int cr_ctx_set_grouping(cr_ctx *c, int64_t max_n) {
+    if (!c || max_n < 0) return CR_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (max_n > 0 && !c->batch) {
+        c->batch = cr_batcher_create(c->device);
+        if (!c->batch) return CR_EDEVICE;
+    }
+    c->group_max_n = max_n;
+    return CR_OK;
+}
+
+extern "C" int cr_ctx_group_stats(cr_ctx *c, double *rounds, double *pass_launches, double *fit_rounds) {
+    if (!c) return CR_EINVAL;
+    if (rounds) *rounds = 0.0;
+    if (pass_launches) *pass_launches = 0.0;
+    if (fit_rounds) *fit_rounds = 0.0;
+    if (c->batch) cr_batcher_stats(c->batch, rounds, pass_launches, fit_rounds);
     return CR_OK;
 }

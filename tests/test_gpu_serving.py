@@ -133,3 +133,24 @@ def test_slot_arenas_are_reused_across_sizes(cr, torch_dev):
         np.testing.assert_array_equal(a.y, m.y)
         np.testing.assert_array_equal(a.xi, m.xi)
         assert a.report["iters"] == m.report["iters"]
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "fp64"])
+def test_grouped_rounds_carry_several_fits(cr, torch_dev, precision):
+    """Small fits submitted together iterate in grouped rounds (one pass launch per kernel variant
+    for all of them), and each result is still bitwise the fit run alone."""
+    reqs = _requests(6, 11)
+    opt = cr.Options(precision=precision, max_iters=2000)
+    alone = [cr.fit(x, yb, 1e-3, 1e-4, opt) for (x, yb) in reqs]
+    with cr.Server(max_slots=6, group_max_n=2048) as srv:
+        ids = [srv.submit(x, yb, 1e-3, 1e-4, opt) for (x, yb) in reqs]
+        served = [srv.wait(i) for i in ids]
+        st = srv.group_stats()
+    for a, m in zip(alone, served):
+        np.testing.assert_array_equal(a.y, m.y)
+        np.testing.assert_array_equal(a.xi, m.xi)
+        assert a.report["iters"] == m.report["iters"]
+    # every trial round of every fit went through the batcher, most of them shared
+    assert st["fit_rounds"] == sum(m.report["trials"] / 2 for m in served)
+    assert st["fit_rounds"] >= 1.5 * st["rounds"]
+    assert st["pass_launches"] < st["fit_rounds"]
