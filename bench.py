@@ -59,14 +59,19 @@ def kernel_hash() -> str:
 #   fp64       : read lam^{k-1}, lam^{k-2}, write lam^k, 8 bytes each                  -> 24
 #   mixed_fp32 : read H (4), l^{k-1} (4), l^{k-2} (4), write l^k (4)                    -> 16
 #   mixed_bf16 : read H (2), l^{k-1} (4), l^{k-2} (4), write l^k (4)                    -> 14
-# adaptive step, dominant pass:
-#   fp64       : trial pass, read lam^k, lam^{k-1}, write two candidates, 8 bytes each      -> 32
-#   mixed_fp32 : re-forming trial pass, read H (4), l^{k-1} (4), l^{k-2} (4), write the
-#                re-formed l^k (4); the two candidates are not stored                     -> 16
+# adaptive step, dominant pass (the re-forming trial pass: it re-forms the previous trial's
+# accepted candidate from the two stored iterates, stores it over the older one, and evaluates
+# this iteration's two candidates without storing them):
+#   mixed_fp32 : read H (4), l^{k-1} (4), l^{k-2} (4), write the re-formed l^k (4)         -> 16
 #   mixed_bf16 : the same with a BF16 H                                                   -> 14
-# (a retry pass of the split forms only reads: 12 / 10 bytes per pair)
+#   fp64 (reform_fp64) : read lam^{k-1}, lam^{k-2}, write the re-formed lam^k, 8 bytes each -> 24
+# the FP64 default instead stores both candidates (one FP64 contraction fewer; the FP64 matrix
+# cores, not HBM, bound that pass):
+#   fp64       : trial pass, read lam^k, lam^{k-1}, write two candidates, 8 bytes each      -> 32
+# (a retry pass only reads: 12 / 10 bytes per pair in the split forms, 16 in FP64)
 PASS_BYTES = {("constant", "fp64"): 24, ("constant", "mixed_fp32"): 16, ("constant", "mixed_bf16"): 14,
-              ("adaptive", "fp64"): 32, ("adaptive", "mixed_fp32"): 16, ("adaptive", "mixed_bf16"): 14}
+              ("adaptive", "fp64"): 32, ("adaptive", "mixed_fp32"): 16, ("adaptive", "mixed_bf16"): 14,
+              ("adaptive", "fp64_reform"): 24}
 _REP = {"fp64": "double,REP_F64", "mixed_fp32": "float,REP_SPLIT_F32", "mixed_bf16": "float,REP_SPLIT_BF16"}
 
 
@@ -84,7 +89,7 @@ def step_kernel_stats(rep: dict, precision: str, rule: str) -> dict:
     low_iters = rep["iters_low"]
     hi_iters = rep["iters"] - rep["iters_low"]
     # launches per accepted iteration of the dominant kernel: 1 for the constant step; for the
-    # adaptive one trials / 2 / iters (FP64) or the re-forming passes per iteration (split forms)
+    # adaptive one trials / 2 / iters (FP64 storing trial) or the re-forming passes per iteration
     if rule != "adaptive":
         per_iter = 1.0
     elif precision == "fp64":
@@ -103,6 +108,8 @@ def step_kernel_stats(rep: dict, precision: str, rule: str) -> dict:
 
 
 def _contractions(rule: str, precision: str) -> int:
+    # residual + adjoint (constant step); two residuals and two candidate adjoints (re-forming
+    # pass); one residual and two candidate adjoints (FP64 storing trial pass)
     if rule != "adaptive":
         return 2
     return 3 if precision == "fp64" else 4
@@ -471,6 +478,20 @@ def main() -> int:
             "mixed_vs_fp64_y_rel": _g4(float(np.max(np.abs(ymix - y64)) / np.max(np.abs(y64)))),
         })
         log(f"fp64 comparison: {rep64['iters']} iters in {dt64:.2f} s")
+        # the FP64 re-forming variant (24 instead of 32 bytes per pair, one FP64 contraction more)
+        optr = cr.Options(precision="fp64", device=0, step_rule=rule, restart=restart, reform_fp64=True,
+                          stream=torch.cuda.current_stream(dev).cuda_stream)
+        cr.fit(x, yb, wl.delta, args.tol, optr)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rr = cr.fit(x, yb, wl.delta, args.tol, optr)
+        torch.cuda.synchronize()
+        dtr = time.perf_counter() - t1
+        msr = rr.report["step_ms_fp64"]
+        compare.update({"fp64_reform_time_to_tol_s": round(dtr, 4), "fp64_reform_iters": rr.report["iters"],
+                        "fp64_reform_pass_ms": round(msr, 4),
+                        "fp64_trial_pass_ms": round(ks64["ms"], 4)})
+        log(f"fp64 re-forming comparison: {rr.report['iters']} iters in {dtr:.3f} s, pass {msr:.3f} ms")
         if args.precision == "mixed_fp32":
             # the other split form (BF16 high part, 14 instead of 16 bytes per pair in the hot pass):
             # context only, never `value`; warmed once, then timed once

@@ -89,7 +89,13 @@ typedef struct {
                                 comes where a geometric decay through the two would reach tol, but
                                 no sooner than check_every / 5 (at least 1) and no later than
                                 check_every iterations; 0: a test every check_every iterations */
-    int32_t reserved[1];
+    int32_t reform_fp64;     /* FP64 mode with the adaptive step.  0 (default): the trial pass stores
+                                both candidates (reads 2, writes 2 FP64 iterates: 32 B per pair;
+                                three FP64 contractions); 1: the next trial pass re-forms the
+                                accepted candidate instead (24 B per pair, a fourth FP64
+                                contraction).  The FP64 matrix cores bound that pass, so the
+                                default is the faster one (measured at N = 8000, n = 40: 0.49 ms
+                                against 0.52 ms).  The split modes always re-form. */
 } cr_options;
 
 typedef struct {

@@ -41,7 +41,7 @@ class CROptions(C.Structure):
         ("restart", C.c_int32),
         ("stop_rule", C.c_int32),
         ("check_rule", C.c_int32),
-        ("reserved", C.c_int32 * 1),
+        ("reform_fp64", C.c_int32),
     ]
 
 
@@ -207,6 +207,8 @@ class Options:
     stop: str = "kkt"               # "kkt": report.kkt <= tol; "gap": certified gap <= tol
     checks: str = "predict"         # "predict": next test at the extrapolated crossing of tol,
                                     # within [check_every / 5, check_every]; "fixed": every check_every
+    reform_fp64: bool = False       # FP64 adaptive step: re-forming trial pass (24 B/pair) instead of
+                                    # storing both candidates (32 B/pair, one FP64 contraction fewer)
 
     def to_c(self) -> CROptions:
         o = CROptions()
@@ -228,6 +230,7 @@ class Options:
         o.restart = 1 if self.restart else 0
         o.stop_rule = {"kkt": 0, "gap": 1}[self.stop]
         o.check_rule = {"fixed": 0, "predict": 1}[self.checks]
+        o.reform_fp64 = 1 if self.reform_fp64 else 0
         return o
 
 

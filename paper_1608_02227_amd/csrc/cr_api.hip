@@ -27,8 +27,8 @@ LamRep rep_of(int precision) {
 
 // bytes of the multiplier state per (padded) pair
 size_t state_bytes_per_pair(LamRep r, bool adaptive) {
-    // FP64 adaptive: two iterates + two stored candidates; split forms re-form the accepted
-    // candidate instead of storing it
+    // FP64 adaptive (storing trial pass): two iterates + two stored candidates; the split forms
+    // re-form the accepted candidate instead of storing it
     if (r == REP_F64) return adaptive ? 32 : 16;
     return 8 + (r == REP_SPLIT_F32 ? 4 : 2);
 }
@@ -166,6 +166,7 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->restart < 0 || opt->restart > 1) return CR_EINVAL;
         if (opt->stop_rule < 0 || opt->stop_rule > 1) return CR_EINVAL;
         if (opt->check_rule < 0 || opt->check_rule > 1) return CR_EINVAL;
+        if (opt->reform_fp64 < 0 || opt->reform_fp64 > 1) return CR_EINVAL;
     }
     return CR_OK;
 }
@@ -179,7 +180,7 @@ int cr_solver::allocate_state(int64_t N, int64_t n) {
 #define CR_ALLOC(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
     CR_ALLOC(lam[0], lamsz);
     CR_ALLOC(lam[1], lamsz);
-    if (adaptive && rep == REP_F64) {
+    if (rep == REP_F64 && fp64_buffers() == 4) {
         CR_ALLOC(lam[2], lamsz);
         CR_ALLOC(lam[3], lamsz);
     }
@@ -233,9 +234,11 @@ int cr_solver::allocate_state(int64_t N, int64_t n) {
         CR_ALLOC(yo64, nr * 8);
         CR_ALLOC(xio64, rows_np * 8);
         CR_ALLOC(dmyo64, nr * 8);
-        CR_ALLOC(yo32, nr * 4);
-        CR_ALLOC(xio32, rows_np * 4);
-        CR_ALLOC(dmyo32, nr * 4);
+        if (fp32pass) {
+            CR_ALLOC(yo32, nr * 4);
+            CR_ALLOC(xio32, rows_np * 4);
+            CR_ALLOC(dmyo32, nr * 4);
+        }
     }
     CR_ALLOC(in_x, (size_t)N * n * 8);
     CR_ALLOC(in_y, (size_t)N * 8);
@@ -278,7 +281,7 @@ size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt_in, int de
     probe.device = -1;
     size_t b = (count.off + 255) & ~(size_t)255;
     if (promotion && probe.rep != REP_F64)
-        b += (probe.adaptive ? 4 : 2) * (((size_t)probe.g.Nr * probe.g.ld * 8 + 255) & ~(size_t)255);
+        b += probe.fp64_buffers() * (((size_t)probe.g.Nr * probe.g.ld * 8 + 255) & ~(size_t)255);
     return b;
 }
 
@@ -560,10 +563,14 @@ int cr_solver::materialize() {
     a.beta_prev = pend_beta;
     a.beta_next = 0.0;
     a.inv_L = pend_invs;
-    a.xhat = xhat32; a.xi = xio32; a.yv = yo32; a.dmy = dmyo32;
+    if (fp32pass) {
+        a.xhat = xhat32; a.xi = xio32; a.yv = yo32; a.dmy = dmyo32;
+    } else {
+        a.xhat = xhat64; a.xi = xio64; a.yv = yo64; a.dmy = dmyo64;
+    }
     a.part_acc = part_acc;
     a.part_col = part_col;
-    CR_HIP(launch_pass(g, PASS_STEP, true, rep, a, stream));
+    CR_HIP(launch_pass(g, PASS_STEP, fp32pass, rep, a, stream));
     std::swap(cur, prv);
     pend = false;
     return CR_OK;
@@ -605,7 +612,8 @@ int cr_solver::step_adaptive() {
             a.beta_prev = pend_beta;
             a.inv_Lo = pend_invs;
             a.beta_next = bk;
-            a.xi_o = xio32; a.yv_o = yo32; a.dmy_o = dmyo32;
+            if (fp32pass) { a.xi_o = xio32; a.yv_o = yo32; a.dmy_o = dmyo32; }
+            else { a.xi_o = xio64; a.yv_o = yo64; a.dmy_o = dmyo64; }
         }
         a.inv_L = 1.0 / sa;
         a.inv_L2 = 1.0 / sb;
@@ -993,7 +1001,7 @@ int cr_solver::promote() {
     test_fresh = false;
     if (rep == REP_F64) return CR_OK;
     const size_t bytes = (size_t)g.Nr * g.ld * 8;
-    const int nbuf = adaptive ? 4 : 2;
+    const int nbuf = fp64_buffers();
     // a workspace promotes only if the FP64 copy fits in what is left of it (checked before any
     // work, so that a refusal leaves the split state untouched)
     if (ws && (((ws->off + 255) & ~(size_t)255) + nbuf * ((bytes + 255) & ~(size_t)255) > ws->size))

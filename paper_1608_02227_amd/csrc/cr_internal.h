@@ -60,7 +60,8 @@ struct cr_solver {
 
     // device buffers (padded as described by Geometry)
     // Multiplier buffers (FP64 matrix, or FP32 low part against lam_hi).  Roles: lam[cur] = lam^k,
-    // lam[prv] = lam^{k-1}; the adaptive step writes its two candidates to lam[fa], lam[fb].
+    // lam[prv] = lam^{k-1}; the FP64 storing trial pass writes its two candidates to lam[fa],
+    // lam[fb] (the re-forming forms store none).
     void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
     int prv = 1, fa = 2, fb = 3;
     void *lam_hi = nullptr;              // split: shared high part
@@ -68,16 +69,19 @@ struct cr_solver {
     double *xhat64 = nullptr, *ybar64 = nullptr;
     double *y64 = nullptr, *xi64 = nullptr, *dmy64 = nullptr;      // eta^{k+1} for the next step
     float *xhat32 = nullptr, *y32 = nullptr, *xi32 = nullptr, *dmy32 = nullptr;
-    // Split forms with the adaptive step: the accepted candidate is not stored by its trial pass;
-    // the next pass re-forms it from the two stored iterates, the accepted step and the pass
-    // arrays of that trial, kept here (swapped with the current ones at each acceptance).
+    // Re-forming forms of the adaptive step (split modes; FP64 with reform_fp64): the accepted
+    // candidate is not stored by its trial pass; the next pass re-forms it from the two stored
+    // iterates, the accepted step and the pass arrays of that trial, kept here (swapped with the
+    // current ones at each acceptance; the FP32 copies in mixed modes).
     double *yo64 = nullptr, *xio64 = nullptr, *dmyo64 = nullptr;
     float *yo32 = nullptr, *xio32 = nullptr, *dmyo32 = nullptr;
     bool pend = false;          // an accepted iterate lam^k is not yet stored
     double pend_beta = 0.0;     // its lam~ = lam[cur] + pend_beta (lam[cur] - lam[prv])
     double pend_invs = 0.0;     // and its step 1 / s_k
     double adv_passes = 0.0;    // re-forming trial passes launched
-    bool deferred() const { return adaptive && rep != cr::REP_F64; }
+    bool deferred() const { return adaptive && (rep != cr::REP_F64 || opt.reform_fp64 != 0); }
+    // FP64 buffers the adaptive step's storing trial pass needs (two iterates + two candidates)
+    int fp64_buffers() const { return adaptive && opt.reform_fp64 == 0 ? 4 : 2; }
     double *yc = nullptr, *xic = nullptr, *dmyc = nullptr;         // eta(lam^k) for tests/output
     double *yr = nullptr, *xir = nullptr, *dmyr = nullptr;         // scratch primal (repair, prime)
     double *rowred = nullptr;

@@ -159,7 +159,6 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     constexpr bool kAdv = (MODE == PASS_ADV);
     constexpr bool kStoreCand = (MODE == PASS_TRIAL);
     constexpr bool kTrial = (MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS || kAdv);
-    static_assert(!(kAdv && REP == REP_F64), "the re-forming trial pass is built for the split forms");
     constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER || MODE == PASS_REBASE ||
                                kTrial);
     // Split-form trial passes take the two adjoints of the candidate differences D on BF16 MFMA with
@@ -380,7 +379,27 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                     cur.b[c >> 2][c & 3] = (float)l0;
                     const T nx = l0 + bn * (l0 - l1);                    // low part of lam~^{k+1}
                     out[c] = ok ? nx : (T)0;
-                } else if constexpr (MODE == PASS_TRIAL && REP == REP_F64) {
+                } else if constexpr (kAdv && REP == REP_F64) {
+                    const T P = (T)cur.p[c], Q = (T)cur.q[c];
+                    // re-form the accepted candidate of the previous trial: lam^k
+                    const T lto = P + bp * (P - Q);
+                    const T so = So[c >> 2][c & 3];
+                    T z = fmax(lto - so * invLo, (T)0);
+                    z = ok ? z : (T)0;
+                    cur.q[c] = (double)z;                                // stored over lam^{k-2}
+                    // trial from (lam^k, lam^{k-1})
+                    const T lt = z + bn * (z - P);                       // lam~^{k+1}
+                    T ta = fmax(lt - s * invL, (T)0);
+                    T tb = fmax(lt - s * invL2, (T)0);
+                    ta = ok ? ta : (T)0;
+                    tb = ok ? tb : (T)0;
+                    out[c] = ok ? ta - lt : (T)0;                        // D_a
+                    out2[c] = ok ? tb - lt : (T)0;                       // D_b
+                    red0 += out[c] * out[c];
+                    red1 += out2[c] * out2[c];
+                    red2 += out[c] * (ta - z);                           // <D_a, cand_a - lam^k>
+                    red3 += out2[c] * (tb - z);
+                } else if constexpr ((MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS) && REP == REP_F64) {
                     const T P = (T)cur.p[c], Q = (T)cur.q[c];
                     const T lt = P + bp * (P - Q);                       // lam~^k
                     T ta = fmax(lt - s * invL, (T)0);                    // candidate with 1 / s_a
@@ -504,7 +523,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                         *reinterpret_cast<f4 *>(pd32 + e + 4) = f4{(float)cand_b[4], (float)cand_b[5], (float)cand_b[6], (float)cand_b[7]};
                     }
                 } else if constexpr (REP == REP_F64) {
-                    if (MODE == PASS_STEP || MODE == PASS_RESID) *reinterpret_cast<d4 *>(pb64 + e) = cur.q;
+                    if (MODE == PASS_STEP || MODE == PASS_RESID || kAdv) *reinterpret_cast<d4 *>(pb64 + e) = cur.q;
                 } else {
                     if (MODE == PASS_STEP || MODE == PASS_REBASE || kAdv) {
                         *reinterpret_cast<f4 *>(pb32 + e) = cur.b[0];
@@ -832,10 +851,12 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, 
         if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_TRIAL>(g, a, st);
         return hipErrorInvalidValue;
     case PASS_TRIAL_NS:
+        if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_TRIAL_NS>(g, a, st);
         if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_TRIAL_NS>(g, a, st);
         if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_TRIAL_NS>(g, a, st);
         return hipErrorInvalidValue;
     case PASS_ADV:
+        if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_ADV>(g, a, st);
         if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_ADV>(g, a, st);
         if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_ADV>(g, a, st);
         return hipErrorInvalidValue;
@@ -881,10 +902,12 @@ hipError_t launch_pass_group(PassMode mode, bool fp32, LamRep rep, const PassGro
         if (!fp32 && rep == REP_F64) return launch_group_mb<double, REP_F64, PASS_TRIAL>(G, st);
         return hipErrorInvalidValue;
     case PASS_TRIAL_NS:
+        if (!fp32 && rep == REP_F64) return launch_group_mb<double, REP_F64, PASS_TRIAL_NS>(G, st);
         if (fp32 && rep == REP_SPLIT_F32) return launch_group_mb<float, REP_SPLIT_F32, PASS_TRIAL_NS>(G, st);
         if (fp32 && rep == REP_SPLIT_BF16) return launch_group_mb<float, REP_SPLIT_BF16, PASS_TRIAL_NS>(G, st);
         return hipErrorInvalidValue;
     case PASS_ADV:
+        if (!fp32 && rep == REP_F64) return launch_group_mb<double, REP_F64, PASS_ADV>(G, st);
         if (fp32 && rep == REP_SPLIT_F32) return launch_group_mb<float, REP_SPLIT_F32, PASS_ADV>(G, st);
         if (fp32 && rep == REP_SPLIT_BF16) return launch_group_mb<float, REP_SPLIT_BF16, PASS_ADV>(G, st);
         return hipErrorInvalidValue;

@@ -28,17 +28,19 @@ def test_more_than_one_gpu_is_refused():
 
 def test_bytes_per_pair_follow_the_stored_state():
     """Bytes per pair of the dominant pass, re-derived from the element sizes: the constant step and
-    the split forms' re-forming trial read H (none in FP64) and two stored iterates and write one;
-    the FP64 trial reads two iterates and writes both candidates."""
+    the re-forming trial passes read H (none in FP64) and two stored iterates and write one; the
+    FP64 storing trial reads two iterates and writes both candidates."""
     b = _bench()
     hi = {"fp64": 0, "mixed_fp32": 4, "mixed_bf16": 2}
     it = {"fp64": 8, "mixed_fp32": 4, "mixed_bf16": 4}
     for p in hi:
         assert b.PASS_BYTES[("constant", p)] == hi[p] + 3 * it[p]
-    assert b.PASS_BYTES[("adaptive", "fp64")] == 4 * it["fp64"]
     for p in ("mixed_fp32", "mixed_bf16"):
         assert b.PASS_BYTES[("adaptive", p)] == hi[p] + 3 * it[p]
+    assert b.PASS_BYTES[("adaptive", "fp64_reform")] == 3 * it["fp64"]
+    assert b.PASS_BYTES[("adaptive", "fp64")] == 4 * it["fp64"]
     assert b.pass_kernel("adaptive", "mixed_fp32") == "pass_kernel<float,REP_SPLIT_F32,PASS_ADV,MB=3,KT=2>"
+    assert b.pass_kernel("adaptive", "fp64") == "pass_kernel<double,REP_F64,PASS_TRIAL,MB=3,KT=2>"
     assert b.pass_kernel("constant", "fp64") == "pass_kernel<double,REP_F64,PASS_STEP,MB=3,KT=2>"
 
 

@@ -202,13 +202,15 @@ def test_converged_fit_mixed_matches_oracle(cr, torch_dev, precision):
 
 # ---- adaptive step (Section 2.4, eq. eq:adaptive-check) -------------------------------------------
 
-@pytest.mark.parametrize("wl,N,seed,momentum,restart", [
-    ("sqnorm_N200_n2", 200, 0, True, False), ("lse8_N2000_n10", 150, 1, True, False),
-    ("quad_N8000_n40", 130, 2, True, False), ("sqnorm_N200_n2", 77, 3, False, False),
-    ("sqnorm_N200_n2", 200, 0, True, True), ("lse8_N2000_n10", 150, 1, True, True),
-    ("quad_N8000_n40", 400, 2, True, True)])
-def test_adaptive_iterates_match_oracle(cr, torch_dev, wl, N, seed, momentum, restart):
-    """Iterates and accepted steps of the adaptive rule against the oracle.
+@pytest.mark.parametrize("wl,N,seed,momentum,restart,reform", [
+    ("sqnorm_N200_n2", 200, 0, True, False, False), ("lse8_N2000_n10", 150, 1, True, False, False),
+    ("quad_N8000_n40", 130, 2, True, False, False), ("sqnorm_N200_n2", 77, 3, False, False, False),
+    ("sqnorm_N200_n2", 200, 0, True, True, False), ("lse8_N2000_n10", 150, 1, True, True, False),
+    ("quad_N8000_n40", 400, 2, True, True, False),
+    ("lse8_N2000_n10", 150, 1, True, False, True), ("quad_N8000_n40", 400, 2, True, True, True)])
+def test_adaptive_iterates_match_oracle(cr, torch_dev, wl, N, seed, momentum, restart, reform):
+    """Iterates and accepted steps of the adaptive rule against the oracle (FP64; `reform`: the
+    trial pass re-forms the accepted candidate instead of storing both).
 
     The accepted steps 1/s_k are up to ~2000x longer than 1/L here, and a step that long
     amplifies rounding-level components along the high-curvature directions of C C^T by up to
@@ -226,7 +228,7 @@ def test_adaptive_iterates_match_oracle(cr, torch_dev, wl, N, seed, momentum, re
     oracle.papg(x, yp, delta, 0.0, L=L, max_iters=50, check_every=10 ** 9, momentum=momentum, iterates=its_p,
                 adaptive=True, restart=restart)
     ref, refp = dict(its), dict(its_p)
-    with cr.Solver(x, ybar, delta, cr.Options(momentum=momentum, restart=restart)) as s:
+    with cr.Solver(x, ybar, delta, cr.Options(momentum=momentum, restart=restart, reform_fp64=reform)) as s:
         s.set_L(L)
         done = 0
         for k in (1, 2, 3, 10, 25, 50):
