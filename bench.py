@@ -333,6 +333,48 @@ def render_line(out: dict) -> str:
     return line
 
 
+def run_probe(torch, cr, N: int, n: int, iters: int) -> dict:
+    """Memory probes (libcr_probe.so) at the pass's geometry for an N-point fit: plain streams over
+    one padded multiplier array's worth of floats per array, and the pass's own access pattern
+    (three 4-byte arrays read, the third written in place) with and without its per-64-column
+    workgroup barrier.  GB/s counts the bytes each kernel must move."""
+    import ctypes as C
+    from paper_1608_02227_amd import build as crbuild
+    if not os.path.exists(crbuild.PROBE_LIB):
+        crbuild.build_probe(verbose=True)
+    lib = C.CDLL(crbuild.PROBE_LIB)
+    lib.cr_probe_stream.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p,
+                                    C.POINTER(C.c_float)]
+    lib.cr_probe_pattern.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.c_int, C.c_void_p, C.POINTER(C.c_float)]
+    geo = cr.pass_geometry(N, n)
+    rows = geo["rows"]
+    nf = rows * rows
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    arrs = [torch.rand(nf, device="cuda", generator=gen) * 1e-3 for _ in range(3)]
+    st = torch.cuda.current_stream().cuda_stream
+    ptr = [C.c_void_p(a.data_ptr()) for a in arrs]
+    ms = C.c_float()
+    out = {"N": N, "n": n, "rows": rows, "chunks": geo["chunks"], "chunk_cols": geo["chunk_cols"],
+           "array_MiB": round(nf * 4 / 2 ** 20, 1), "iters": iters}
+    for kind, name, narr in [(0, "read", 1), (1, "copy", 2), (2, "read2_write1", 3), (3, "read3_write1_inplace", 4)]:
+        rc = lib.cr_probe_stream(kind, ptr[0], ptr[1], ptr[2], nf, iters, st, C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"cr_probe_stream({kind}) failed: {rc}")
+        out[f"stream_{name}_GBs"] = round(narr * nf * 4 / (ms.value * 1e-3) / 1e9, 1)
+    for barrier in (0, 1):
+        rc = lib.cr_probe_pattern(ptr[0], ptr[1], ptr[2], rows, rows, geo["chunks"], geo["chunk_cols"], barrier,
+                                  iters, st, C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"cr_probe_pattern failed: {rc}")
+        key = "pattern_barrier" if barrier else "pattern"
+        out[f"{key}_us"] = round(ms.value * 1e3, 1)
+        out[f"{key}_GBs"] = round(16 * nf / (ms.value * 1e-3) / 1e9, 1)
+        # the same time charged to the pass's algorithmic bytes (16 B per real pair)
+        out[f"{key}_alg_GBs"] = round(16 * N * (N - 1) / (ms.value * 1e-3) / 1e9, 1)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +410,9 @@ def main() -> int:
                     help="also fit the N=40000, n=20 workload to tol, at most K iterations (0: skip)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the N=200 and N=2000 configurations (FP64 and mixed, to tolerance)")
+    ap.add_argument("--probe", type=int, default=0, metavar="N",
+                    help="only run the memory probes at the pass geometry of an N-point, n=40 fit and print "
+                         "their JSON line (no fits)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -387,6 +432,9 @@ def main() -> int:
     if not os.path.exists(crbuild.LIB):   # a tree that was never built: build it (loading is strict)
         crbuild.build(verbose=True)
     cr.load()
+    if args.probe > 0:
+        print(json.dumps({"probe": run_probe(torch, cr, args.probe, 40, 20)}), flush=True)
+        return 0
     dev = torch.device("cuda:0")
     wl = W.WORKLOADS[WORKLOAD]
     x_h, yb_h = W.make(WORKLOAD, seed=args.seed)

@@ -295,6 +295,12 @@ int cr_solver_get_primal(cr_solver *s, double *y, double *xi);
 /* FP64 stopping report of lam^k (and the certificate if opt.certificate). */
 int cr_solver_report(cr_solver *s, cr_report *rep);
 
+/* Tiling of the pair sweep for an N-point, n-feature fit on `device` (diagnostics and memory
+ * probes): padded rows (= the multiplier arrays' leading dimension), column chunks per 128-row
+ * strip, columns per chunk, and workgroups per pass. */
+int cr_pass_geometry(int64_t N, int64_t n, int device, int32_t *rows, int32_t *chunks,
+                     int32_t *chunk_cols, int32_t *workgroups);
+
 /* ---- Operators on device data (one call each; device pointers, synchronous). ------------ */
 /* s = C eta: s_ij = y_j - y_i + xi_i^T (x_i - x_j), zero diagonal; s is N x N (Def. "def:A1A2"). */
 int cr_op_residual(int64_t N, int64_t n, const double *x, const double *y, const double *xi,

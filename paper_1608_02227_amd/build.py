@@ -41,6 +41,25 @@ def _compile(src: str, defines=(), objdir: str = OBJ) -> str:
     return obj
 
 
+PROBE_SOURCE = "cr_probe.hip"
+PROBE_LIB = os.path.join(HERE, "libcr_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The memory probes (libcr_probe.so): a separate library, not part of the fit path."""
+    os.makedirs(OBJ, exist_ok=True)
+    obj = _compile(PROBE_SOURCE)
+    tmp = PROBE_LIB + ".tmp"
+    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, "-o", tmp],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
+
+
 def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
     """Compile every source and link `out` (default: the package's libcr.so)."""
     objdir = OBJ if not defines else os.path.join(OBJ, "_".join(d.replace("=", "") for d in defines))
@@ -60,4 +79,5 @@ def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_probe(verbose=True)
     sys.exit(0)

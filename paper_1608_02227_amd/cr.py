@@ -161,6 +161,7 @@ def load() -> C.CDLL:
         "cr_ctx_group_stats": (C.c_int, [vp, _P(d), _P(d), _P(d)]),
         "cr_ctx_set_grouping": (C.c_int, [vp, i64]),
         "cr_fit_state_bytes": (C.c_size_t, [i64, i64, i32]),
+        "cr_pass_geometry": (C.c_int, [i64, i64, C.c_int, _P(i32), _P(i32), _P(i32), _P(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -441,6 +442,13 @@ def op_adjoint(x, lam, device: int = 0):
     _check(load().cr_op_adjoint(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(lam.data_ptr()), C.c_void_p(u.data_ptr()),
                                 C.c_void_p(w.data_ptr()), device), "op_adjoint")
     return u, w
+
+
+def pass_geometry(N: int, n: int, device: int = 0) -> dict:
+    """Tiling of the pair sweep (cr_pass_geometry): padded rows, chunks, columns per chunk, workgroups."""
+    r, c, cc, wg = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().cr_pass_geometry(N, n, device, C.byref(r), C.byref(c), C.byref(cc), C.byref(wg)), "geometry")
+    return {"rows": r.value, "chunks": c.value, "chunk_cols": cc.value, "workgroups": wg.value}
 
 
 def state_bytes(N: int, n: int, precision: str = "fp64") -> int:

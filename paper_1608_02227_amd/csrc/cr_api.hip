@@ -1442,6 +1442,21 @@ extern "C" int cr_fit_device(int64_t N, int64_t n, const double *x, const double
     return cr_fit_impl(N, n, x, ybar, delta, tol, opt, y, xi, lambda, rep, true);
 }
 
+extern "C" int cr_pass_geometry(int64_t N, int64_t n, int device, int32_t *rows, int32_t *chunks,
+                                int32_t *chunk_cols, int32_t *workgroups) {
+    if (N < 1 || n < 1 || n + 1 > 16 * kMaxMB || N > 200000) return CR_EINVAL;
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    const Geometry g = make_geometry((int)N, (int)n, cus);
+    if (rows) *rows = g.Nr;
+    if (chunks) *chunks = g.chunks;
+    if (chunk_cols) *chunk_cols = g.chunk_cols;
+    if (workgroups) *workgroups = g.grid();
+    return CR_OK;
+}
+
 // ---- operators --------------------------------------------------------------------------------
 
 extern "C" int cr_op_residual(int64_t N, int64_t n, const double *x, const double *y, const double *xi, double *s_out,

@@ -57,6 +57,16 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
+// Two values at once: hi = RNE(x) in BF16 (one packed conversion for the pair), lo = RNE(x - hi);
+// the same numbers as split_bf16 on each.  hp, lp receive the pair packed (first value low).
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16_pair(float x0, float x1, uint32_t &hp, uint32_t &lp) {
+    hp = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{x0, x1}, b2));
+    const float h0 = __uint_as_float(hp << 16), h1 = __uint_as_float(hp & 0xFFFF0000u);
+    lp = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{x0 - h0, x1 - h1}, b2));
+}
+
 // ---- multiplier storage -------------------------------------------------------------------
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 // Round-to-nearest-even of a finite float to BF16.
@@ -158,6 +168,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     constexpr bool kSplit = (REP != REP_F64);
     constexpr bool kAdv = (MODE == PASS_ADV);
     constexpr bool kStoreCand = (MODE == PASS_TRIAL);
+    static_assert(!(kStoreCand && REP != REP_F64), "only the FP64 trial pass stores its candidates");
     constexpr bool kTrial = (MODE == PASS_TRIAL || MODE == PASS_TRIAL_NS || kAdv);
     constexpr bool kAdjoint = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_POWER || MODE == PASS_REBASE ||
                                kTrial);
@@ -202,6 +213,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     const int cend = min(g.ld, cbeg + g.chunk_cols);
     const int nsup = (cend - cbeg) / kSuper;
     const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L, invL2 = (T)a.inv_L2;
+    // Split trial passes: rows 8..15 of each wave evaluate the candidates in the order (b, a), so
+    // that the first exchange of the column-sum reduce-scatter needs no selects (every lane keeps
+    // `out` and sends `out2`); their trial sums and adjoint accumulators are swapped back at the end.
+    const bool cswap = kBfAdj && ((lr >> 3) & 1);
+    const T invA = cswap ? invL2 : invL, invB = cswap ? invL : invL2;
     const T invLo = (T)a.inv_Lo;
     const bool rebase_lam = (MODE == PASS_REBASE) && a.rebase_lam != 0;
     // Output rows of the 16x16x4 MFMA: lane group g, item v receives row 4 g + v in the FP32 form
@@ -247,8 +263,6 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     uint16_t *phb = static_cast<uint16_t *>(a.lam_h);
     double *pc64 = static_cast<double *>(a.lam_c);
     double *pd64 = static_cast<double *>(a.lam_d);
-    float *pc32 = static_cast<float *>(a.lam_c);
-    float *pd32 = static_cast<float *>(a.lam_d);
 
     auto load_tile = [&](int j0, Raw<REP> &t) {
         const size_t e = rowoff + j0;
@@ -426,8 +440,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                     // trial from (lam^k, lam^{k-1})
                     const T m = z - l1;
                     const T lt = z + bn * m;
-                    T la = fmax(lt - s * invL, -H);
-                    T lb = fmax(lt - s * invL2, -H);
+                    T la = fmax(lt - s * invA, -H);                    // (b for swapped rows)
+                    T lb = fmax(lt - s * invB, -H);
                     la = ok ? la : (T)0;
                     lb = ok ? lb : (T)0;
                     out[c] = ok ? la - lt : (T)0;
@@ -442,12 +456,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                     const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
                     const T m = l1 - l2;
                     const T lt = l1 + bp * m;                            // low part of lam~^k
-                    T la = fmax(lt - s * invL, -H);
-                    T lb = fmax(lt - s * invL2, -H);
+                    T la = fmax(lt - s * invA, -H);                    // (b for swapped rows)
+                    T lb = fmax(lt - s * invB, -H);
                     la = ok ? la : (T)0;
                     lb = ok ? lb : (T)0;
-                    cand_a[c] = la;
-                    cand_b[c] = lb;
                     out[c] = ok ? la - lt : (T)0;
                     out2[c] = ok ? lb - lt : (T)0;
                     tr0 += out[c] * out[c];
@@ -511,17 +523,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
             {
                 const size_t e = rowoff + j0;
                 if constexpr (kStoreCand) {
-                    if constexpr (REP == REP_F64) {
-                        *reinterpret_cast<d4 *>(pc64 + e) = d4{(double)cand_a[0], (double)cand_a[1],
-                                                               (double)cand_a[2], (double)cand_a[3]};
-                        *reinterpret_cast<d4 *>(pd64 + e) = d4{(double)cand_b[0], (double)cand_b[1],
-                                                               (double)cand_b[2], (double)cand_b[3]};
-                    } else {
-                        *reinterpret_cast<f4 *>(pc32 + e) = f4{(float)cand_a[0], (float)cand_a[1], (float)cand_a[2], (float)cand_a[3]};
-                        *reinterpret_cast<f4 *>(pc32 + e + 4) = f4{(float)cand_a[4], (float)cand_a[5], (float)cand_a[6], (float)cand_a[7]};
-                        *reinterpret_cast<f4 *>(pd32 + e) = f4{(float)cand_b[0], (float)cand_b[1], (float)cand_b[2], (float)cand_b[3]};
-                        *reinterpret_cast<f4 *>(pd32 + e + 4) = f4{(float)cand_b[4], (float)cand_b[5], (float)cand_b[6], (float)cand_b[7]};
-                    }
+                    *reinterpret_cast<d4 *>(pc64 + e) = d4{(double)cand_a[0], (double)cand_a[1],
+                                                           (double)cand_a[2], (double)cand_a[3]};
+                    *reinterpret_cast<d4 *>(pd64 + e) = d4{(double)cand_b[0], (double)cand_b[1],
+                                                           (double)cand_b[2], (double)cand_b[3]};
                 } else if constexpr (REP == REP_F64) {
                     if (MODE == PASS_STEP || MODE == PASS_RESID || kAdv) *reinterpret_cast<d4 *>(pb64 + e) = cur.q;
                 } else {
@@ -546,15 +551,19 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                 static_assert(CPL == 8, "the BF16 adjoint takes a lane's 8 consecutive columns as its K slice");
                 // A[m][k] = Xhat[column jl + 8 lq + k][feature 16 mb + lr]; B[k][n] = D[row lr][column
                 // jl + 8 lq + k]
-                bf8 dh, dl, eh, el;
+                uint4 dhu, dlu, ehu, elu;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    __bf16 h, lo;
-                    split_bf16((float)out[c], h, lo);
-                    dh[c] = h; dl[c] = lo;
-                    split_bf16((float)out2[c], h, lo);
-                    eh[c] = h; el[c] = lo;
+                for (int c2 = 0; c2 < 4; ++c2) {
+                    uint32_t hp, lp;
+                    split_bf16_pair((float)out[2 * c2], (float)out[2 * c2 + 1], hp, lp);
+                    u4_set(dhu, c2, hp);
+                    u4_set(dlu, c2, lp);
+                    split_bf16_pair((float)out2[2 * c2], (float)out2[2 * c2 + 1], hp, lp);
+                    u4_set(ehu, c2, hp);
+                    u4_set(elu, c2, lp);
                 }
+                const bf8 dh = __builtin_bit_cast(bf8, dhu), dl = __builtin_bit_cast(bf8, dlu);
+                const bf8 eh = __builtin_bit_cast(bf8, ehu), el = __builtin_bit_cast(bf8, elu);
                 const __bf16 *xth = sXTh + b * NP * XTS + jl + 8 * lq;
                 const __bf16 *xtl = sXTl + b * NP * XTS + jl + 8 * lq;
 #pragma unroll
@@ -582,7 +591,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                 T v8[8], v4[4], v2[2];
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    v8[q] = (h3 ? out2[q] : out[q]) + dpp_move<0x128>(h3 ? out[q] : out2[q]);    // row_ror:8
+                    v8[q] = out[q] + dpp_move<0x128>(out2[q]);    // row_ror:8 (rows 8..15 hold b in `out`)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     v4[q] = (h2 ? v8[4 + q] : v8[q]) + dpp_move<0x141>(h2 ? v8[q] : v8[4 + q]);  // row_half_mirror
@@ -686,8 +695,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
 
     if (kAdjoint) {
         // D layout: lane (lr, lq) holds rows m = 16 mb + 4 lq + r of (Lam Xhat)^T for row i.
-        T *pacc = static_cast<T *>(a.part_acc) + ((size_t)chunk * g.Nr + i) * NP;
-        T *pacc2 = kTrial ? static_cast<T *>(a.part_acc2) + ((size_t)chunk * g.Nr + i) * NP : nullptr;
+        // swapped rows accumulated candidate b in acc and a in acc2
+        T *pacc = static_cast<T *>(cswap ? a.part_acc2 : a.part_acc) + ((size_t)chunk * g.Nr + i) * NP;
+        T *pacc2 = kTrial ? static_cast<T *>(cswap ? a.part_acc : a.part_acc2) + ((size_t)chunk * g.Nr + i) * NP
+                          : nullptr;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             if (sizeof(T) == 8) {
@@ -710,6 +721,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     }
 
     if (MODE == PASS_KKT || MODE == PASS_POWER || kTrial) {
+        if (cswap) {
+            const double t0 = red0, t2 = red2;
+            red0 = red1; red1 = t0;
+            red2 = red3; red3 = t2;
+        }
         for (int m = 32; m >= 1; m >>= 1) {
             red0 = (MODE == PASS_KKT) ? fmax(red0, __shfl_xor(red0, m, 64)) : red0 + __shfl_xor(red0, m, 64);
             red1 = kTrial ? red1 + __shfl_xor(red1, m, 64) : fmax(red1, __shfl_xor(red1, m, 64));
@@ -845,10 +861,8 @@ hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep, 
     case PASS_RESID:
         if (fp32 || rep != REP_F64) return hipErrorInvalidValue;
         return launch_mb<double, REP_F64, PASS_RESID>(g, a, st);
-    case PASS_TRIAL:
+    case PASS_TRIAL:   // the storing trial pass (FP64); the split forms re-form instead
         if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_TRIAL>(g, a, st);
-        if (fp32 && rep == REP_SPLIT_F32) return launch_mb<float, REP_SPLIT_F32, PASS_TRIAL>(g, a, st);
-        if (fp32 && rep == REP_SPLIT_BF16) return launch_mb<float, REP_SPLIT_BF16, PASS_TRIAL>(g, a, st);
         return hipErrorInvalidValue;
     case PASS_TRIAL_NS:
         if (!fp32 && rep == REP_F64) return launch_mb<double, REP_F64, PASS_TRIAL_NS>(g, a, st);
