@@ -55,17 +55,21 @@ def test_continuation_obeys_the_bound_and_is_certified(seed, kind, n):
     x, ybar = _problem(seed, n=n, kind=kind)
     ex = oracle.exact_ls(x, ybar)
     xs = np.linalg.norm(ex["xi"])
-    out = oracle.continuation(x, ybar, eps0=1.0, beta=2.0, kappa_gamma=1.0, kappa_delta=1.0, T=10)
+    out = oracle.continuation(x, ybar, eps0=1.0, beta=2.0, kappa_gamma=0.5, kappa_delta=1.0, T=10)
     for o in out:
-        assert o["gamma"] == pytest.approx(1.0 / 2.0 ** o["t"], rel=1e-15)
-        assert o["delta"] == o["gamma"]
-        assert o["status"] == "converged" and o["cert_gap"] <= o["delta"]
+        # Section 2.4.1's schedule, from the parameters: eps_t = eps0 / beta^t, gamma_t = kappa_gamma
+        # eps_t, delta_t = kappa_delta eps_t (distinct kappas, so a swapped weight shows)
+        eps_t = 1.0 / 2.0 ** o["t"]
+        gamma_t, delta_t = 0.5 * eps_t, eps_t
+        assert o["gamma"] == pytest.approx(gamma_t, rel=1e-15)
+        assert o["delta"] == pytest.approx(delta_t, rel=1e-15)
+        assert o["status"] == "converged" and o["cert_gap"] <= delta_t
         # Section 2.4.1: ||y^(t) - y*|| <= ||xi*|| sqrt(gamma_t) + sqrt(2 delta_t)
-        assert np.linalg.norm(o["y"] - ex["y"]) <= xs * math.sqrt(o["gamma"]) + math.sqrt(2 * o["delta"])
+        assert np.linalg.norm(o["y"] - ex["y"]) <= xs * math.sqrt(gamma_t) + math.sqrt(2 * delta_t)
         # the certificate is honest: the true dual suboptimality at gamma_t is at most delta_t
-        exg = oracle.exact_solve(x, ybar, o["gamma"])
-        g = oracle.dual_objective(x, ybar, o["gamma"], o["lam"])
-        assert exg["p_star"] - g <= o["delta"] + 1e-12
+        exg = oracle.exact_solve(x, ybar, gamma_t)
+        g = oracle.dual_objective(x, ybar, gamma_t, o["lam"])
+        assert exg["p_star"] - g <= delta_t + 1e-12
         assert exg["p_star"] - g <= o["cert_gap"] + 1e-12
     # the iterates approach y*
     d = [np.linalg.norm(o["y"] - ex["y"]) for o in out]
