@@ -4,6 +4,8 @@
 
 #include "cr_internal.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -11,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 using namespace cr;
@@ -38,6 +41,46 @@ bool all_finite(const double *p, size_t n) {
         if (!std::isfinite(p[i])) return false;
     return true;
 }
+
+// Phase ranges for profilers (roctx): "cr_fit", "preprocess", "iterate", "stopping_test",
+// "certificate".  The roctx library is looked up at run time (libroctx64, or the rocprofiler-sdk
+// one); without it the ranges cost nothing.  rocprofv3 --marker-trace records them.
+struct Roctx {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+};
+const Roctx &roctx() {
+    static Roctx r;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (const char *lib : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4", "libroctx64.so"}) {
+            void *h = dlopen(lib, RTLD_NOW | RTLD_LOCAL | RTLD_NOLOAD);
+            if (!h) h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+            if (!h) continue;
+            auto push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+            auto pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+            if (push && pop) { r.push = push; r.pop = pop; break; }
+        }
+    });
+    return r;
+}
+struct Range {
+    explicit Range(const char *name) { if (roctx().push) roctx().push(name); }
+    ~Range() { if (roctx().pop) roctx().pop(); }
+};
+
+// Per-test trace (environment CR_TRACE): a path receives one JSON line per stopping test
+// (appended); any other value prints a line per test to stderr.
+FILE *trace_file() {
+    static FILE *f = nullptr;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *v = getenv("CR_TRACE");
+        if (v && std::strchr(v, '/')) f = std::fopen(v, "a");
+    });
+    return f;
+}
+std::mutex trace_mu;
 
 }  // namespace
 
@@ -838,6 +881,7 @@ void cr_solver::collect_timing() {
 }
 
 int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
+    const Range r("preprocess");
     test_fresh = false;   // the power passes reuse scal and the pass arrays
     const double t0 = now_s();
     CR_HIP(hipSetDevice(device));
@@ -1075,6 +1119,7 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
                 if (rc) return rc;
             }
             const Iterating it(adaptive ? batch : nullptr);
+            const Range r("iterate");
             for (int64_t q = 0; q < std::min<int64_t>(opt.check_every, kmax); ++q) {
                 rc = adaptive ? step_adaptive() : step_once();
                 if (rc) break;
@@ -1083,9 +1128,24 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
             if (rc) return rc;
             continue;
         }
-        int rc = check(&rep, by_gap);
+        int rc;
+        {
+            const Range r("stopping_test");
+            rc = check(&rep, by_gap);
+        }
         ++checks;
-        if (trace)
+        if (trace && trace_file()) {
+            std::lock_guard<std::mutex> lk(trace_mu);
+            fprintf(trace_file(),
+                    "{\"fit\": \"%p\", \"N\": %d, \"n\": %d, \"k\": %lld, \"t_s\": %.6f, \"kkt\": %.6e, "
+                    "\"max_viol\": %.6e, \"infeas_rms\": %.6e, \"dual_gap_paper\": %.6e, \"comp_sum\": %.9e, "
+                    "\"dual_obj\": %.15e, \"primal_obj\": %.15e, \"low_precision\": %d, \"step_over_L\": %.6e, "
+                    "\"trial_passes\": %.0f, \"restarts\": %.0f}\n",
+                    (void *)this, g.N, g.n, (long long)k, now_s() - t0, rep.kkt, rep.max_viol, rep.infeas_rms,
+                    rep.dual_gap_paper, rep.comp_sum, rep.dual_obj, rep.primal_obj, fp32pass ? 1 : 0,
+                    adaptive ? s_step / L : 1.0, trials / 2.0, restarts);
+            fflush(trace_file());
+        } else if (trace)
             fprintf(stderr, "cr trace: k=%lld kkt=%.4e viol=%.4e infeas=%.4e dual=%.12e low=%d s/L=%.3e trials=%.0f "
                     "t=%.3f\n", (long long)k, rep.kkt, rep.max_viol, rep.infeas_rms, rep.dual_obj, fp32pass ? 1 : 0,
                     adaptive ? s_step / L : 1.0, trials, now_s() - t0);
@@ -1130,6 +1190,7 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
             if (rc) return rc;
         }
         const Iterating it(adaptive && todo > 0 ? batch : nullptr);
+        const Range r("iterate");
         for (int64_t q = 0; q < todo; ++q) {
             rc = adaptive ? step_adaptive() : step_once();
             if (rc == CR_ENUMERIC) { status = CR_ENUMERIC; break; }
@@ -1138,6 +1199,7 @@ int cr_solver::solve(double tol, cr_report *rep_out) {
         if (status == CR_ENUMERIC) break;
     }
     if (opt.certificate) {
+        const Range r("certificate");
         int rc = check(&rep, true);
         if (rc && rc != CR_ENUMERIC) return rc;
         if (rc == CR_ENUMERIC) status = CR_ENUMERIC;
@@ -1315,6 +1377,7 @@ static int fit_trivial(int64_t N, int64_t n, const double *ybar, double *y, doub
 int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, double delta, double tol,
                 const cr_options *opt_in, double *y, double *xi, double *lambda, cr_report *rep, bool dev,
                 cr_workspace *ws, double *pinned_scal, cr_batcher *batch, hipEvent_t ev_ready) {
+    const Range range("cr_fit");
     const double t0 = now_s();
     cr_options opt;
     if (opt_in) opt = *opt_in; else cr_default_options(&opt);

@@ -567,3 +567,31 @@ def test_adaptive_without_momentum_mixed_matches_oracle(cr, torch_dev, restart):
     assert np.max(np.abs(lam - ref)) <= 1e-4 * np.abs(ref).max()
     assert np.all(lam >= 0.0) and np.all(np.diag(lam) == 0.0)
     assert rep["adv_passes"] > 0
+
+
+def test_per_test_jsonl_trace(tmp_path):
+    """CR_TRACE=<path>: one JSON line per stopping test of a fit, in iteration order, the last one
+    matching the fit's report (run in a child process: the trace file is opened once per process)."""
+    import subprocess
+    import sys
+    path = tmp_path / "trace.jsonl"
+    code = (
+        "import json, sys\n"
+        "sys.path.insert(0, %r)\n"
+        "from paper_1608_02227_amd import cr, workloads as W\n"
+        "x, yb = W.make('lse8_N2000_n10', seed=2, N=300)\n"
+        "r = cr.fit(x, yb, 1e-3, 1e-5, cr.Options(precision='mixed_fp32'))\n"
+        "print(json.dumps(r.report))\n" % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    env = dict(os.environ)
+    env["CR_TRACE"] = str(path)
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    rep = json.loads(res.stdout.strip().splitlines()[-1])
+    lines = [json.loads(l) for l in path.read_text().splitlines()]
+    assert len(lines) == rep["checks"]              # every test of the loop (the certificate is not one)
+    ks = [l["k"] for l in lines]
+    assert ks == sorted(ks) and ks[-1] == rep["iters"]
+    assert lines[-1]["kkt"] == pytest.approx(rep["kkt"], rel=1e-6)
+    assert lines[-1]["dual_obj"] == pytest.approx(rep["dual_obj"], rel=1e-12)
+    assert all(l["N"] == 300 and l["n"] == 10 for l in lines)
+    assert lines[-1]["kkt"] <= 1e-5 < lines[0]["kkt"]
