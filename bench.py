@@ -613,7 +613,7 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64", "fp64": "f64"}[args.precision],
-        "data": "synthetic (seeded generator, same shapes and distributions as the named workload)",
+        "data": "synthetic (seeded; the named workload's shapes and distributions)",
         "config": {"workload": f"{WORKLOAD}: x~U[-1,1]^40, f0=x'Qx, Q=M'M/40, eps~N(0,0.5^2)",
                    "N": wl.N, "n": wl.n, "delta": wl.delta, "tol": args.tol, "precision": args.precision,
                    "step_rule": rule, "momentum_restart": restart,
@@ -637,9 +637,8 @@ def main() -> int:
         out["compare"] = compare
     if other_seeds:
         out["other_seeds"] = other_seeds
-    out["paper_context"] = ("no number for this variant or workload; the paper's largest runs (PAPG_A, K=N/100 "
-                            "blocks with MOSEK sub-QPs, MATLAB FP64, 24-core node): N=2400 n=80 quadratic "
-                            "897 s, exp 774 s wall (Tables xqx_80, exp_80)")
+    out["paper_context"] = ("none for this variant/workload; paper's largest (PAPG_A, K=N/100 MOSEK sub-QPs, "
+                            "MATLAB FP64, 24 cores): N=2400 n=80 897 s quad, 774 s exp")
     print(render_line(out), flush=True)
     return 0
 

@@ -65,6 +65,8 @@ CASES = [
     ("c1_sqnorm_N200_n2_seed0_tol1e-10", "sqnorm_N200_n2", "mixed_bf16", 1e-6, 1e-4),
     ("c2_lse8_N2000_n10_seed0_tol1e-8", "lse8_N2000_n10", "fp64", 1e-8, 1e-6),
     ("c2_lse8_N2000_n10_seed0_tol1e-8", "lse8_N2000_n10", "mixed_fp32", 1e-6, 1e-4),
+    ("c2_lse8_N2000_n10_seed0_tol1e-8", "lse8_N2000_n10", "mixed_bf16", 1e-6, 1e-4),
+    ("c1_sqnorm_N200_n2_seed0_tol1e-10", "sqnorm_N200_n2", "fp64_reform", 1e-9, 1e-6),
 ]
 
 
@@ -74,7 +76,8 @@ def test_converged_config_fit_matches_oracle(cr, torch_dev, ref, wl, precision, 
     x, ybar = W.make(wl, seed=meta["seed"])
     assert x.shape == (meta["N"], meta["n"])
     print(f"converged fit {wl} {precision} tol {tol}", flush=True)
-    r = cr.fit(x, ybar, meta["delta"], tol, cr.Options(precision=precision), allow_noconv=False)
+    opt = cr.Options(precision="fp64", reform_fp64=True) if precision == "fp64_reform" else cr.Options(precision=precision)
+    r = cr.fit(x, ybar, meta["delta"], tol, opt, allow_noconv=False)
     _check(r, y_ref, xi_ref, meta, tol, ybar_rel)
 
 
