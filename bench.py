@@ -337,7 +337,8 @@ def run_probe(torch, cr, N: int, n: int, iters: int) -> dict:
     """Memory probes (libcr_probe.so) at the pass's geometry for an N-point fit: plain streams over
     one padded multiplier array's worth of floats per array, and the pass's own access pattern
     (three 4-byte arrays read, the third written in place) with and without its per-64-column
-    workgroup barrier.  GB/s counts the bytes each kernel must move."""
+    workgroup barrier, walking every chunk in one direction or alternately forwards and backwards.
+    GB/s counts the bytes each kernel must move."""
     import ctypes as C
     from paper_1608_02227_amd import build as crbuild
     if not os.path.exists(crbuild.PROBE_LIB):
@@ -362,12 +363,14 @@ def run_probe(torch, cr, N: int, n: int, iters: int) -> dict:
         if rc != 0:
             raise RuntimeError(f"cr_probe_stream({kind}) failed: {rc}")
         out[f"stream_{name}_GBs"] = round(narr * nf * 4 / (ms.value * 1e-3) / 1e9, 1)
-    for barrier in (0, 1):
-        rc = lib.cr_probe_pattern(ptr[0], ptr[1], ptr[2], rows, rows, geo["chunks"], geo["chunk_cols"], barrier,
+    # flags: bit 0 the pass's barrier per 64 columns, bit 1 every other launch walking its columns
+    # backwards (starting on what the previous launch touched last)
+    for flags, key in [(0, "pattern"), (1, "pattern_barrier"), (2, "pattern_alternating"),
+                       (3, "pattern_barrier_alternating")]:
+        rc = lib.cr_probe_pattern(ptr[0], ptr[1], ptr[2], rows, rows, geo["chunks"], geo["chunk_cols"], flags,
                                   iters, st, C.byref(ms))
         if rc != 0:
             raise RuntimeError(f"cr_probe_pattern failed: {rc}")
-        key = "pattern_barrier" if barrier else "pattern"
         out[f"{key}_us"] = round(ms.value * 1e3, 1)
         out[f"{key}_GBs"] = round(16 * nf / (ms.value * 1e-3) / 1e9, 1)
         # the same time charged to the pass's algorithmic bytes (16 B per real pair)

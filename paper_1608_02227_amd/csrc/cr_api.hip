@@ -481,6 +481,7 @@ extern "C" int cr_solver_destroy(cr_solver *s) {
 int cr_solver::adjoint_to(int idx, double *y, double *xi, double *dmy, bool with_rowred, float *y32_, float *xi32_,
                           float *dmy32_) {
     PassArgs a{};
+    a.rev = next_sweep();
     a.lam_h = lam_hi;
     a.lam_a = lam[idx];
     a.xhat = xhat64;
@@ -512,6 +513,7 @@ int cr_solver::rebase(bool *eta_in_yc) {
     if (rc) return rc;
     if (rep == REP_F64) return CR_OK;
     PassArgs a{};
+    a.rev = next_sweep();
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[prv];
@@ -600,6 +602,7 @@ int cr_solver::refresh_eta(bool have_cur_in_yc) {
 int cr_solver::materialize() {
     if (!pend) return CR_OK;
     PassArgs a{};
+    a.rev = next_sweep();
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[prv];
@@ -643,6 +646,7 @@ int cr_solver::step_adaptive() {
         // split forms: the first attempt also re-forms and stores the previous accepted iterate
         const bool adv = defer && pend;
         PassArgs a{};
+        a.rev = next_sweep();
         a.lam_h = lam_hi;
         a.lam_a = lam[cur];
         a.lam_b = lam[prv];
@@ -805,6 +809,7 @@ int cr_solver::step_once() {
     const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
     const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
     PassArgs a{};
+    a.rev = next_sweep();
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[prv];
@@ -949,6 +954,7 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
             if (rc) return rc;
         }
         PassArgs a{};
+        a.rev = next_sweep();
         a.lam_h = lam_hi;
         a.lam_a = lam[cur];
         a.xhat = xhat64; a.xi = xic; a.yv = yc; a.dmy = dmyc;

@@ -135,6 +135,9 @@ struct cr_solver {
     double L = 0.0, sigma2 = 0.0, preprocess_s = 0.0;
     int power_iters = 0;
     int64_t k = 0, k_low = 0, checked_k = -1;
+    // column walking direction of the next multiplier sweep (alternates, see PassArgs::rev)
+    int sweep_rev = 0;
+    int next_sweep() { const int r = sweep_rev; sweep_rev ^= 1; return r; }
     // the last stopping test's device results (eta(lam^k) in yc / xic / dmyc, the KKT reductions in
     // scal[0..5]) still describe the current iterate; cleared by anything that moves it
     bool test_fresh = false;

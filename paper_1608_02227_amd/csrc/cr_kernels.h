@@ -118,6 +118,10 @@ struct PassArgs {
     // PASS_REBASE only: 0 accumulates the adjoint of the new high part H', 1 that of lam^k as
     // stored after the re-basing (H' + l_k')
     int rebase_lam;
+    // 1: every workgroup walks its column chunk from the end back to the start (the fit alternates
+    // the direction from one multiplier sweep to the next, so that a sweep starts on the lines the
+    // previous one touched last, which the last-level cache still holds)
+    int rev;
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,

@@ -212,6 +212,9 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     const int cbeg = chunk * g.chunk_cols;
     const int cend = min(g.ld, cbeg + g.chunk_cols);
     const int nsup = (cend - cbeg) / kSuper;
+    // first column of the s-th super tile in walking order (a.rev: from the end of the chunk back)
+    const bool rev = a.rev != 0;
+    auto sup_col = [&](int s) { return cbeg + (rev ? nsup - 1 - s : s) * kSuper; };
     const T bp = (T)a.beta_prev, bn = (T)a.beta_next, invL = (T)a.inv_L, invL2 = (T)a.inv_L2;
     // Split trial passes: rows 8..15 of each wave evaluate the candidates in the order (b, a), so
     // that the first exchange of the column-sum reduce-scatter needs no selects (every lane keeps
@@ -281,26 +284,27 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     };
 
     // stage super tile 0 and prefetch the first two tiles' multipliers
+    const int c0 = sup_col(0);
     if (nsup > 0) {
         for (int e = tid; e < kSuper * NP; e += NT) {
             const int jj = e / NP, m = e - jj * NP;
-            const T v = xhat[(size_t)(cbeg + jj) * NP + m];
+            const T v = xhat[(size_t)(c0 + jj) * NP + m];
             sX[jj * SX + m] = v;
             if constexpr (kBfAdj) split_bf16((float)v, sXTh[m * XTS + jj], sXTl[m * XTS + jj]);
         }
-        if (tid < kSuper) sY[tid] = kResidual ? yv[cbeg + tid] : (T)0;
-        if (kAdv && tid < kSuper) sYo[tid] = yvo[cbeg + tid];
+        if (tid < kSuper) sY[tid] = kResidual ? yv[c0 + tid] : (T)0;
+        if (kAdv && tid < kSuper) sYo[tid] = yvo[c0 + tid];
     }
     static_assert(TPS % 2 == 0, "the two-deep prefetch ring needs an even number of tiles per super tile");
     Raw<REP> pf[2];
     if (kLoads && nsup > 0) {
-        load_tile(cbeg + CPL * lq, pf[0]);
-        load_tile(cbeg + TW + CPL * lq, pf[1]);
+        load_tile(c0 + CPL * lq, pf[0]);
+        load_tile(c0 + TW + CPL * lq, pf[1]);
     }
     __syncthreads();
 
     for (int st = 0; st < nsup; ++st) {
-        const int cst = cbeg + st * kSuper;
+        const int cst = sup_col(st);
         const int b = st & 1;
         const T *sXb = sX + b * BUF;
         const T *sYb = sY + b * kSuper;
@@ -308,7 +312,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
 
         // register prefetch of the next super tile's locations (the last super tile re-reads its
         // own rows instead, so the loads need no branch)
-        const int cnx = more ? cst + kSuper : cst;
+        const int cnx = more ? sup_col(st + 1) : cst;
         T xr[XR];
 #pragma unroll
         for (int q = 0; q < XR; ++q) xr[q] = xhat[(size_t)cnx * NP + tid + q * NT];
@@ -323,10 +327,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
             const int j0 = cst + jc;                 // global column of c = 0
             Raw<REP> cur = pf[t & 1];
             if (kLoads) {
-                // two tiles ahead (possibly in the next super tile); past the end of the chunk the
-                // current tile is re-read instead, so the load needs no branch
-                const int jn = j0 + 2 * TW;
-                load_tile(jn < cend ? jn : j0, pf[t & 1]);
+                // two tiles ahead in walking order (possibly in the next super tile); past the last
+                // tile the current one is re-read instead, so the load needs no branch
+                const int sn = st + (t + 2) / TPS;
+                const int jn = sn < nsup ? sup_col(sn) + ((t + 2) % TPS) * TW + CPL * lq : j0;
+                load_tile(jn, pf[t & 1]);
             }
             // keep the prefetch ahead of this tile's work (the scheduler would otherwise sink the
             // loads below the epilogue, which then waits for them)

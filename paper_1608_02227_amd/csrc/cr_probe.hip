@@ -10,7 +10,10 @@
 //                       column chunks), waves of 16 rows, lanes holding 8 consecutive columns of one
 //                       row, 32-column tiles prefetched two ahead in registers, the third array
 //                       written in place; optionally one workgroup barrier per 64 columns as in the
-//                       pass.  Arithmetic: one fused multiply-add and one max per element.
+//                       pass, and optionally every other launch walking its columns from the end of
+//                       the chunk back to its start (so that a launch begins where the previous one
+//                       ended, on the lines the last-level cache still holds).  Arithmetic: one fused
+//                       multiply-add and one max per element.
 // Both time `iters` launches with HIP events on the given stream and return the average ms.
 
 #include <hip/hip_runtime.h>
@@ -46,7 +49,7 @@ constexpr int kSuper = 64;   // columns per barrier interval
 
 template <bool BARRIER>
 __global__ __launch_bounds__(512) void pattern_kernel(const float *H, const float *A, float *B, int ld, int chunks,
-                                                      int chunk_cols) {
+                                                      int chunk_cols, int rev) {
     __shared__ float sink[512];
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, lr = l & 15, lq = l >> 4;
@@ -65,16 +68,17 @@ __global__ __launch_bounds__(512) void pattern_kernel(const float *H, const floa
     };
     Raw pf[2];
     const int ntiles = (cend - cbeg) / 32;
-    if (ntiles > 0) load(cbeg + 8 * lq, pf[0]);
-    if (ntiles > 1) load(cbeg + 32 + 8 * lq, pf[1]);
+    // column of tile number t in the walking order
+    auto col = [&](int t) { return cbeg + (rev ? ntiles - 1 - t : t) * 32 + 8 * lq; };
+    if (ntiles > 0) load(col(0), pf[0]);
+    if (ntiles > 1) load(col(1), pf[1]);
     float keep = 0.f;
     for (int t = 0; t < ntiles; t += 2) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int j0 = cbeg + (t + u) * 32 + 8 * lq;
+            const int j0 = col(t + u);
             Raw cur = pf[u];
-            const int jn = j0 + 64;
-            load(jn < cend ? jn : j0, pf[u]);
+            load(t + u + 2 < ntiles ? col(t + u + 2) : j0, pf[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
@@ -119,23 +123,27 @@ extern "C" int cr_probe_stream(int kind, const void *a, const void *b, void *c, 
 }
 
 // rows: padded row count (a multiple of 128, = ld); chunks, chunk_cols: the pass's column split
-// (chunk_cols a multiple of 64).  Arrays are rows x ld floats.
+// (chunk_cols a multiple of 64).  Arrays are rows x ld floats.  flags: bit 0 the per-64-column
+// barrier, bit 1 every odd-numbered launch walks its columns backwards.
 extern "C" int cr_probe_pattern(const void *H, const void *A, void *B, int rows, int ld, int chunks, int chunk_cols,
-                                int barrier, int iters, void *stream, float *ms_out) {
+                                int flags, int iters, void *stream, float *ms_out) {
     if (!H || !A || !B || rows % kRows || chunk_cols % kSuper || chunks < 1 || iters < 1 || !ms_out ||
-        (long)chunks * chunk_cols < ld)
+        (long)chunks * chunk_cols < ld || ld % kSuper || flags < 0 || flags > 3)
         return -1;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -5;
     const dim3 grid((rows / kRows) * chunks), block(512);
+    int launch = 0;
     auto go = [&]() {
-        if (barrier)
+        const int rev = (flags & 2) ? (launch & 1) : 0;
+        ++launch;
+        if (flags & 1)
             hipLaunchKernelGGL(pattern_kernel<true>, grid, block, 0, st, (const float *)H, (const float *)A,
-                               (float *)B, ld, chunks, chunk_cols);
+                               (float *)B, ld, chunks, chunk_cols, rev);
         else
             hipLaunchKernelGGL(pattern_kernel<false>, grid, block, 0, st, (const float *)H, (const float *)A,
-                               (float *)B, ld, chunks, chunk_cols);
+                               (float *)B, ld, chunks, chunk_cols, rev);
     };
     go();
     (void)hipEventRecord(e0, st);
