@@ -96,6 +96,20 @@ typedef struct {
                                 contraction).  The FP64 matrix cores bound that pass, so the
                                 default is the faster one (measured at N = 8000, n = 40: 0.49 ms
                                 against 0.52 ms).  The split modes always re-form. */
+    int32_t center;          /* mixed modes: 1 (default) works in the frame x - mean(x) (every pair
+                                constraint and the adjoint depend only on differences x_i - x_j, so
+                                y, xi and lam are the same, and the FP32 residual loses less to
+                                cancellation); 0 keeps the caller's coordinates.  FP64 mode always
+                                keeps them. */
+    int32_t keep_lambda;     /* serving (cr_submit): 1 keeps the request's final multipliers (N x N
+                                FP64, host) until they are collected through the lambda argument of
+                                cr_wait / cr_poll; 0 (default) drops them.  Ignored elsewhere. */
+    const double *lambda0;   /* optional N x N warm start lam^0 (its diagonal is ignored; entries
+                                must be finite and >= 0, else CR_EINVAL), in the memory of the call's
+                                other inputs: host for cr_fit / cr_fit_continuation / cr_submit (which
+                                copies it), device for cr_fit_device / cr_fit_device_noalloc.  NULL
+                                (default): lam^0 = 0 (Theorem "bound").  cr_solver_create's own
+                                lambda0 argument, when given, takes precedence. */
 } cr_options;
 
 typedef struct {
@@ -316,19 +330,26 @@ typedef struct cr_ctx cr_ctx;
  * device memory); max_slots: fits resident at once.  Each slot owns a stream, a small pinned
  * host buffer and a device arena that grows to the largest fit the slot has run and is then
  * reused (fits allocate nothing while the arena is large enough); the arenas are freed by
- * cr_ctx_destroy. */
+ * cr_ctx_destroy.  The context takes no caller stream: its fits overlap on the device because
+ * each slot runs on a stream of its own, and one shared stream would serialize them (a single
+ * fit on a caller's stream is cr_fit_device with opt->stream). */
 int cr_ctx_create(int device, size_t byte_budget, int32_t max_slots, cr_ctx **out);
 /* Running fits finish; queued ones are dropped and their waiters (cr_wait) return CR_ECANCELED.
  * Returns once no thread is inside a call on ctx any more; ctx is then invalid. */
 int cr_ctx_destroy(cr_ctx *ctx);
-/* Queues a fit (copies x, ybar); non-blocking.  Returns its id in *req_id. */
+/* Queues a fit (copies x, ybar and a warm start opt->lambda0); non-blocking.  Returns its id in
+ * *req_id. */
 int cr_submit(cr_ctx *ctx, int64_t N, int64_t n, const double *x, const double *ybar,
               double delta, double tol, const cr_options *opt, int64_t *req_id);
-/* Non-blocking: CR_EAGAIN while running, else the fit's status; results copied out once. */
-int cr_poll(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
+/* Non-blocking: CR_EAGAIN while running, else the fit's status; results copied out once, after
+ * which the id is unknown.  y (N), xi (N x n), rep, latency_s (submission to completion) may each
+ * be NULL.  lambda (N x N, host) receives the final multipliers and needs the request to have been
+ * submitted with opt->keep_lambda = 1; otherwise a non-NULL lambda returns CR_EINVAL and leaves the
+ * result in place. */
+int cr_poll(cr_ctx *ctx, int64_t req_id, double *y, double *xi, double *lambda, cr_report *rep,
             double *latency_s);
 /* Blocking version of cr_poll. */
-int cr_wait(cr_ctx *ctx, int64_t req_id, double *y, double *xi, cr_report *rep,
+int cr_wait(cr_ctx *ctx, int64_t req_id, double *y, double *xi, double *lambda, cr_report *rep,
             double *latency_s);
 /* Device bytes the serving context reserves for one fit of this shape and precision with the
  * default step rule (its whole device state: the multiplier iterates, the partial sums and the

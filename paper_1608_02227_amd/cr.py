@@ -42,6 +42,9 @@ class CROptions(C.Structure):
         ("stop_rule", C.c_int32),
         ("check_rule", C.c_int32),
         ("reform_fp64", C.c_int32),
+        ("center", C.c_int32),
+        ("keep_lambda", C.c_int32),
+        ("lambda0", C.c_void_p),
     ]
 
 
@@ -155,8 +158,8 @@ def load() -> C.CDLL:
         "cr_ctx_create": (C.c_int, [C.c_int, C.c_size_t, i32, _P(vp)]),
         "cr_ctx_destroy": (C.c_int, [vp]),
         "cr_submit": (C.c_int, [vp, i64, i64, vp, vp, d, d, _P(CROptions), _P(i64)]),
-        "cr_poll": (C.c_int, [vp, i64, vp, vp, _P(CRReport), _P(d)]),
-        "cr_wait": (C.c_int, [vp, i64, vp, vp, _P(CRReport), _P(d)]),
+        "cr_poll": (C.c_int, [vp, i64, vp, vp, vp, _P(CRReport), _P(d)]),
+        "cr_wait": (C.c_int, [vp, i64, vp, vp, vp, _P(CRReport), _P(d)]),
         "cr_ctx_stats": (C.c_int, [vp, _P(i64), _P(i64), _P(i64), _P(C.c_size_t)]),
         "cr_ctx_group_stats": (C.c_int, [vp, _P(d), _P(d), _P(d)]),
         "cr_ctx_set_grouping": (C.c_int, [vp, i64]),
@@ -210,6 +213,8 @@ class Options:
                                     # within [check_every / 5, check_every]; "fixed": every check_every
     reform_fp64: bool = False       # FP64 adaptive step: re-forming trial pass (24 B/pair) instead of
                                     # storing both candidates (32 B/pair, one FP64 contraction fewer)
+    center: bool = True             # mixed modes: work in the frame x - mean(x) (results unchanged)
+    keep_lambda: bool = False       # Server: keep each request's final multipliers for wait / poll
 
     def to_c(self) -> CROptions:
         o = CROptions()
@@ -232,6 +237,8 @@ class Options:
         o.stop_rule = {"kkt": 0, "gap": 1}[self.stop]
         o.check_rule = {"fixed": 0, "predict": 1}[self.checks]
         o.reform_fp64 = 1 if self.reform_fp64 else 0
+        o.center = 1 if self.center else 0
+        o.keep_lambda = 1 if self.keep_lambda else 0
         return o
 
 
@@ -261,11 +268,12 @@ class FitResult:
 
 
 def fit(x, ybar, delta: float, tol: float, options: Options | None = None, return_lambda: bool = False,
-        allow_noconv: bool = True, no_alloc: bool = False) -> FitResult:
+        allow_noconv: bool = True, no_alloc: bool = False, lambda0=None) -> FitResult:
     """One complete fit (cr_fit / cr_fit_device).  Device tensors in -> device tensors out.
 
     ``no_alloc`` (device tensors only) calls cr_fit_device_noalloc: the fit runs in the library's
-    fixed scratch array instead of allocating device memory (outputs are still the caller's)."""
+    fixed scratch array instead of allocating device memory (outputs are still the caller's).
+    ``lambda0`` (N x N, same kind as ``x``) is a warm start for the multipliers."""
     lib = load()
     opt = options or Options()
     rep = CRReport()
@@ -284,10 +292,15 @@ def fit(x, ybar, delta: float, tol: float, options: Options | None = None, retur
             opt = Options(**{**opt.__dict__, "stream": torch.cuda.current_stream(x.device).cuda_stream,
                              "device": x.device.index or 0})
         co = opt.to_c()
+        if lambda0 is not None:
+            if not _is_torch_device(lambda0) or tuple(lambda0.shape) != (N, N):
+                raise ValueError("lambda0 must be an N x N device tensor like x")
+            lambda0 = lambda0.contiguous().to(torch.float64)
+            co.lambda0 = lambda0.data_ptr()
         entry = lib.cr_fit_device_noalloc if no_alloc else lib.cr_fit_device
         code = entry(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(ybar.data_ptr()), delta, tol,
-                                 C.byref(co), C.c_void_p(y.data_ptr()), C.c_void_p(xi.data_ptr()),
-                                 C.c_void_p(lam.data_ptr()) if lam is not None else None, C.byref(rep))
+                     C.byref(co), C.c_void_p(y.data_ptr()), C.c_void_p(xi.data_ptr()),
+                     C.c_void_p(lam.data_ptr()) if lam is not None else None, C.byref(rep))
     else:
         x = _host(x)
         N, n = x.shape
@@ -296,6 +309,9 @@ def fit(x, ybar, delta: float, tol: float, options: Options | None = None, retur
         xi = np.empty((N, n))
         lam = np.empty((N, N)) if return_lambda else None
         co = opt.to_c()
+        if lambda0 is not None:
+            lambda0 = _host(lambda0, (N, N))
+            co.lambda0 = lambda0.ctypes.data
         code = lib.cr_fit(N, n, _ptr(x), _ptr(ybar), delta, tol, C.byref(co), _ptr(y), _ptr(xi),
                           _ptr(lam) if lam is not None else None, C.byref(rep))
     _check(code, "cr_fit", allow)
@@ -482,29 +498,35 @@ class Server:
     def __exit__(self, *a):
         self.close()
 
-    def submit(self, x, ybar, delta: float, tol: float, options: Options | None = None) -> int:
+    def submit(self, x, ybar, delta: float, tol: float, options: Options | None = None, lambda0=None) -> int:
+        """Queues a fit; ``lambda0`` (N x N, host) is an optional warm start, copied at submission."""
         x = _host(x)
         N, n = x.shape
         ybar = _host(ybar, (N,))
         rid = C.c_int64()
-        co = (options or Options()).to_c()
+        opt = options or Options()
+        co = opt.to_c()
+        if lambda0 is not None:
+            lambda0 = _host(lambda0, (N, N))
+            co.lambda0 = lambda0.ctypes.data
         _check(load().cr_submit(self._h, N, n, _ptr(x), _ptr(ybar), delta, tol, C.byref(co), C.byref(rid)),
                "cr_submit")
-        self._shapes[rid.value] = (N, n)
+        self._shapes[rid.value] = (N, n, bool(opt.keep_lambda))
         return rid.value
 
     def _collect(self, fn, rid):
-        N, n = self._shapes[rid]
+        N, n, keep = self._shapes[rid]
         y = np.empty(N)
         xi = np.empty((N, n))
+        lam = np.empty((N, N)) if keep else None
         rep = CRReport()
         lat = C.c_double()
-        code = fn(self._h, rid, _ptr(y), _ptr(xi), C.byref(rep), C.byref(lat))
+        code = fn(self._h, rid, _ptr(y), _ptr(xi), _ptr(lam) if keep else None, C.byref(rep), C.byref(lat))
         if code == CR_EAGAIN:
             return None
         _check(code, "collect", (CR_OK, CR_ENOCONV))
         del self._shapes[rid]
-        return FitResult(y, xi, None, rep.as_dict(), code, {"latency_s": lat.value})
+        return FitResult(y, xi, lam, rep.as_dict(), code, {"latency_s": lat.value})
 
     def wait(self, rid: int) -> FitResult:
         return self._collect(load().cr_wait, rid)

@@ -114,6 +114,9 @@ extern "C" void cr_default_options(cr_options *opt) {
     opt->upsilon = 2.0;
     opt->restart = 1;
     opt->check_rule = 1;
+    opt->center = 1;
+    opt->keep_lambda = 0;
+    opt->lambda0 = nullptr;
 }
 
 extern "C" const char *cr_strerror(int code) {
@@ -154,6 +157,8 @@ int cr_solver::alloc(void **p, size_t bytes) {
             return CR_ENOMEM;
         }
         *p = ws->counting ? nullptr : ws->base + at;
+        ws->last = static_cast<char *>(*p);
+        ws->last_off = ws->off;
         ws->off = at + bytes;
         return CR_OK;
     }
@@ -168,7 +173,15 @@ int cr_solver::alloc(void **p, size_t bytes) {
 }
 
 void cr_solver::release(void *p) {
-    if (!p || ws) return;
+    if (!p) return;
+    if (ws) {
+        // only the latest carve can be given back (temporary staging); anything else stays
+        if (p == ws->last) {
+            ws->off = ws->last_off;
+            ws->last = nullptr;
+        }
+        return;
+    }
     for (size_t k = 0; k < owned.size(); ++k)
         if (owned[k] == p) {
             (void)hipFree(p);
@@ -210,6 +223,7 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->stop_rule < 0 || opt->stop_rule > 1) return CR_EINVAL;
         if (opt->check_rule < 0 || opt->check_rule > 1) return CR_EINVAL;
         if (opt->reform_fp64 < 0 || opt->reform_fp64 > 1) return CR_EINVAL;
+        if (opt->center < 0 || opt->center > 1 || opt->keep_lambda < 0 || opt->keep_lambda > 1) return CR_EINVAL;
     }
     return CR_OK;
 }
@@ -322,9 +336,13 @@ size_t cr_workspace_bytes(int64_t N, int64_t n, const cr_options *opt_in, int de
     if (probe.allocate_state(N, n) != CR_OK) return 0;
     probe.ws = nullptr;
     probe.device = -1;
-    size_t b = (count.off + 255) & ~(size_t)255;
+    const size_t state = (count.off + 255) & ~(size_t)255;
+    size_t b = state;
     if (promotion && probe.rep != REP_F64)
         b += probe.fp64_buffers() * (((size_t)probe.g.Nr * probe.g.ld * 8 + 255) & ~(size_t)255);
+    // a warm start is staged as a dense N x N FP64 matrix right behind the state, before anything
+    // else is carved (it fits in the promotion room when there is one)
+    if (opt.lambda0) b = std::max(b, state + (size_t)N * N * 8);
     return b;
 }
 
@@ -359,6 +377,7 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     for (double v : hy) { ymin = std::min(ymin, v); ymax = std::max(ymax, v); }
     s->scale = std::max(1.0, ymax - ymin);
     s->yrange = ymax - ymin;
+    if (!lambda0) lambda0 = opt.lambda0;
     s->lam_zero = (lambda0 == nullptr);
 
     auto bail = [&](int code) { delete s; return code; };
@@ -413,7 +432,8 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
     s->xspan = 0.0;
     for (int64_t i = 0; i < N; ++i)
         for (int64_t m = 0; m < n; ++m) s->xspan = std::max(s->xspan, std::fabs(hx[(size_t)i * n + m] - mu[m]));
-    if (!s->fp32pass) std::fill(mu.begin(), mu.end(), 0.0);   // the FP64 mode keeps the caller's frame
+    // the FP64 mode keeps the caller's frame, and so do the mixed modes with opt.center = 0
+    if (!s->fp32pass || !opt.center) std::fill(mu.begin(), mu.end(), 0.0);
     int rc2 = CR_OK;
     auto H = [&](hipError_t e) { if (e != hipSuccess && rc2 == CR_OK) rc2 = fail_hip(e, "setup"); };
     // a workspace keeps whatever the previous fit left there: clear all of it first
@@ -1310,6 +1330,21 @@ extern "C" int cr_solver_get_lambda_rows(cr_solver *s, int64_t row0, int64_t nro
     return CR_OK;
 }
 
+// A workspace fit copies lam^k to the host in row blocks staged in its column-partial buffer
+// (strips x ld doubles, free once the iterations have ended), so it needs no further device memory.
+int cr_solver::lambda_rows_via_scratch(double *lambda) {
+    const int64_t N = g.N;
+    const int64_t rows = std::max<int64_t>(1, ((int64_t)g.strips * g.ld) / N);
+    for (int64_t r0 = 0; r0 < N; r0 += rows) {
+        const int nr = (int)std::min<int64_t>(rows, N - r0);
+        CR_HIP(launch_unpack_rows(g, rep, rep == REP_F64 ? lam[cur] : lam_hi, (const float *)lam[cur], (int)r0, nr,
+                                  static_cast<double *>(part_col), stream));
+        CR_HIP(hipMemcpyAsync(lambda + r0 * N, part_col, (size_t)nr * N * 8, hipMemcpyDeviceToHost, stream));
+        CR_HIP(hipStreamSynchronize(stream));
+    }
+    return CR_OK;
+}
+
 static int primal_out(cr_solver *s, const double *ysrc, const double *xisrc, double *y, double *xi, bool device_out) {
     const size_t N = s->g.N, n = s->g.n;
     double *dy = nullptr, *dxi = nullptr;
@@ -1416,6 +1451,9 @@ int cr_fit_impl(int64_t N, int64_t n, const double *x, const double *ybar, doubl
             if (launch_unpack_lambda(s->g, s->rep, s->rep == REP_F64 ? s->lam[s->cur] : s->lam_hi,
                                      (const float *)s->lam[s->cur], lambda, s->stream) != hipSuccess ||
                 hipStreamSynchronize(s->stream) != hipSuccess) { delete s; return CR_EDEVICE; }
+        } else if (ws) {
+            rc = s->lambda_rows_via_scratch(lambda);
+            if (rc) { delete s; return rc; }
         } else {
             rc = cr_solver_get_lambda(s, lambda);
             if (rc) { delete s; return rc; }

@@ -14,6 +14,10 @@ struct cr_workspace {
     size_t size = 0;
     size_t off = 0;
     bool counting = false;
+    // the most recent piece carved and the offset before it: releasing that piece (a temporary
+    // staging buffer) gives its bytes back
+    char *last = nullptr;
+    size_t last_off = 0;
 };
 
 struct cr_batcher;
@@ -169,6 +173,7 @@ struct cr_solver {
     int step_adaptive();
     int refresh_eta(bool have_cur_in_yc);
     int materialize();
+    int lambda_rows_via_scratch(double *lambda);
     int lipschitz(double *L, double *s2, int32_t *it);
     int check(cr_report *rep, bool certificate);
     int promote();

@@ -42,6 +42,8 @@ struct Request {
     int state = 0;  // 0 queued, 1 running, 2 done
     int status = CR_OK;
     std::vector<double> y, xi;
+    std::vector<double> lam0;    // warm start (opt.lambda0, copied at submission)
+    std::vector<double> lam;     // final multipliers (opt.keep_lambda)
     cr_report rep{};
 };
 
@@ -140,11 +142,17 @@ struct cr_ctx {
         cr_options o = r->opt;
         o.device = device;
         o.stream = sl.stream;
+        o.lambda0 = r->lam0.empty() ? nullptr : r->lam0.data();
         r->y.assign((size_t)r->N, 0.0);
         r->xi.assign((size_t)(r->N * r->n), 0.0);
+        double *lam_out = nullptr;
+        if (r->opt.keep_lambda) {
+            r->lam.assign((size_t)(r->N * r->N), 0.0);
+            lam_out = r->lam.data();
+        }
         if (r->N == 1) {
             r->status = cr_fit(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
-                               r->xi.data(), nullptr, &r->rep);
+                               r->xi.data(), lam_out, &r->rep);
         } else {
             r->status = reserve(sl, r->bytes);
             if (r->status == CR_OK) {
@@ -152,13 +160,15 @@ struct cr_ctx {
                 ws.base = sl.arena;
                 ws.size = sl.cap;
                 r->status = cr_fit_impl(r->N, r->n, r->x.data(), r->ybar.data(), r->delta, r->tol, &o, r->y.data(),
-                                        r->xi.data(), nullptr, &r->rep, false, &ws, sl.h_scal, b,
+                                        r->xi.data(), lam_out, &r->rep, false, &ws, sl.h_scal, b,
                                         b ? sl.ready : nullptr);
             }
         }
         r->t_done = now_s();
         r->x.clear();
         r->x.shrink_to_fit();
+        r->lam0.clear();
+        r->lam0.shrink_to_fit();
     }
 };
 
@@ -265,7 +275,11 @@ extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const
     r->tol = tol;
     if (opt) r->opt = *opt; else cr_default_options(&r->opt);
     if (r->opt.precision < CR_FP64 || r->opt.precision > CR_MIXED_BF16) return CR_EINVAL;
+    if (r->opt.keep_lambda < 0 || r->opt.keep_lambda > 1) return CR_EINVAL;
+    // sized with the warm start still set (its staging), which then lives in the request
     r->bytes = request_bytes(N, n, r->opt, c->device);
+    if (r->opt.lambda0) r->lam0.assign(r->opt.lambda0, r->opt.lambda0 + (size_t)(N * N));
+    r->opt.lambda0 = nullptr;
     if (N > 1 && r->bytes == 0) return CR_EINVAL;
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(c->mu);
@@ -279,10 +293,12 @@ extern "C" int cr_submit(cr_ctx *c, int64_t N, int64_t n, const double *x, const
     return CR_OK;
 }
 
-static int collect(cr_ctx *c, Request *r, int64_t id, double *y, double *xi, cr_report *rep, double *lat) {
+static int collect(cr_ctx *c, Request *r, int64_t id, double *y, double *xi, double *lambda, cr_report *rep,
+                   double *lat) {
     if (r->status != CR_ECANCELED) {
         if (y) std::memcpy(y, r->y.data(), r->y.size() * 8);
         if (xi) std::memcpy(xi, r->xi.data(), r->xi.size() * 8);
+        if (lambda) std::memcpy(lambda, r->lam.data(), r->lam.size() * 8);
         if (rep) *rep = r->rep;
     }
     if (lat) *lat = r->t_done - r->t_submit;
@@ -291,24 +307,28 @@ static int collect(cr_ctx *c, Request *r, int64_t id, double *y, double *xi, cr_
     return st;
 }
 
-extern "C" int cr_poll(cr_ctx *c, int64_t id, double *y, double *xi, cr_report *rep, double *latency_s) {
+extern "C" int cr_poll(cr_ctx *c, int64_t id, double *y, double *xi, double *lambda, cr_report *rep,
+                       double *latency_s) {
     if (!c) return CR_EINVAL;
     std::lock_guard<std::mutex> lk(c->mu);
     auto it = c->reqs.find(id);
     if (it == c->reqs.end()) return CR_ENOTFOUND;
+    if (lambda && !it->second->opt.keep_lambda) return CR_EINVAL;
     if (it->second->state != 2) return CR_EAGAIN;
-    return collect(c, it->second.get(), id, y, xi, rep, latency_s);
+    return collect(c, it->second.get(), id, y, xi, lambda, rep, latency_s);
 }
 
-extern "C" int cr_wait(cr_ctx *c, int64_t id, double *y, double *xi, cr_report *rep, double *latency_s) {
+extern "C" int cr_wait(cr_ctx *c, int64_t id, double *y, double *xi, double *lambda, cr_report *rep,
+                       double *latency_s) {
     if (!c) return CR_EINVAL;
     std::unique_lock<std::mutex> lk(c->mu);
     auto it = c->reqs.find(id);
     if (it == c->reqs.end()) return CR_ENOTFOUND;
     Request *r = it->second.get();
+    if (lambda && !r->opt.keep_lambda) return CR_EINVAL;
     ++c->waiters;
     c->cv_done.wait(lk, [&] { return r->state == 2; });
-    const int st = collect(c, r, id, y, xi, rep, latency_s);
+    const int st = collect(c, r, id, y, xi, lambda, rep, latency_s);
     if (--c->waiters == 0) c->cv_idle.notify_all();
     return st;
 }

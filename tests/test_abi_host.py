@@ -61,7 +61,8 @@ def test_fit_rejects_bad_options_on_host(cr):
     xi = np.zeros((4, 2))
     for field, value in [("check_every", 0), ("precision", 7), ("L", -1.0), ("power_max_iters", 0),
                          ("step_rule", 2), ("upsilon", 1.0), ("upsilon", float("inf")), ("restart", 2),
-                         ("power_rtol", -1.0), ("stop_rule", 2), ("check_rule", 2), ("check_rule", -1)]:
+                         ("power_rtol", -1.0), ("stop_rule", 2), ("check_rule", 2), ("check_rule", -1),
+                         ("center", 2), ("center", -1), ("keep_lambda", 2)]:
         opt = cr.Options().to_c()
         setattr(opt, field, value)
         rc = lib.cr_fit(4, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)
@@ -148,6 +149,13 @@ def test_noalloc_sizes_on_host(cr):
     assert all(s % 256 == 0 for s in sizes)
     assert sizes[2] >= 2048 * 2048 * 12
     assert cr.noalloc_required_bytes(10, 64, mixed) == 0      # n + 1 > 64 is invalid
+    # a warm start is staged as a dense N x N FP64 matrix behind the state
+    lib = cr.load()
+    for opt in (fp64, mixed):
+        co = opt.to_c()
+        plain = lib.cr_noalloc_required_bytes(1000, 40, C.byref(co))
+        co.lambda0 = 8     # never read by the sizing
+        assert lib.cr_noalloc_required_bytes(1000, 40, C.byref(co)) == plain + 1000 * 1000 * 8
 
 
 def test_noalloc_without_device_fails_loudly(cr):

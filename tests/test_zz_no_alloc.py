@@ -47,6 +47,23 @@ def test_noalloc_equals_fit_device(cr, torch_dev, precision, calls):
         assert got.report["step_samples_low"] == 0 and got.report["step_samples_fp64"] == 0
 
 
+@pytest.mark.parametrize("precision", ["mixed_fp32", "fp64"])
+def test_noalloc_warm_start_equals_fit_device(cr, torch_dev, precision):
+    """A warm start (opt.lambda0, device memory) staged in the scratch behind the state."""
+    torch = torch_dev
+    x, ybar = W.make("lse8_N2000_n10", seed=6, N=700)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(ybar).cuda()
+    opt = cr.Options(precision=precision)
+    start = cr.fit(xd, yd + 0.01, 1e-3, 1e-3, opt, return_lambda=True).lam * 0.7
+    print(f"noalloc warm start: {precision}", flush=True)
+    ref = cr.fit(xd, yd, 1e-3, 1e-4, opt, return_lambda=True, lambda0=start)
+    got = cr.fit(xd, yd, 1e-3, 1e-4, opt, return_lambda=True, lambda0=start, no_alloc=True)
+    torch.cuda.synchronize()
+    for a, b in [(got.y, ref.y), (got.xi, ref.xi), (got.lam, ref.lam)]:
+        assert torch.equal(a, b)
+    assert got.report["iters"] == ref.report["iters"]
+
+
 def test_noalloc_refuses_shapes_beyond_the_scratch(cr, torch_dev):
     torch = torch_dev
     N, n = 3000, 40
