@@ -434,6 +434,16 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         for (int64_t m = 0; m < n; ++m) s->xspan = std::max(s->xspan, std::fabs(hx[(size_t)i * n + m] - mu[m]));
     // the FP64 mode keeps the caller's frame, and so do the mixed modes with opt.center = 0
     if (!s->fp32pass || !opt.center) std::fill(mu.begin(), mu.end(), 0.0);
+    {
+        // the FP16 residual's location scale: a power of two taking max |Xhat| (the stored
+        // locations and the ones column) into [0.5, 1)
+        double xm = 1.0;
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t m = 0; m < n; ++m) xm = std::max(xm, std::fabs((double)(float)(hx[(size_t)i * n + m] - mu[m])));
+        int e = 0;
+        (void)std::frexp(xm, &e);
+        s->xscale = (float)std::ldexp(1.0, -std::min(40, std::max(-40, e)));
+    }
     int rc2 = CR_OK;
     auto H = [&](hipError_t e) { if (e != hipSuccess && rc2 == CR_OK) rc2 = fail_hip(e, "setup"); };
     // a workspace keeps whatever the previous fit left there: clear all of it first
@@ -502,6 +512,7 @@ int cr_solver::adjoint_to(int idx, double *y, double *xi, double *dmy, bool with
                           float *dmy32_) {
     PassArgs a{};
     a.rev = next_sweep();
+    a.x_scale = xscale;
     a.lam_h = lam_hi;
     a.lam_a = lam[idx];
     a.xhat = xhat64;
@@ -534,6 +545,7 @@ int cr_solver::rebase(bool *eta_in_yc) {
     if (rep == REP_F64) return CR_OK;
     PassArgs a{};
     a.rev = next_sweep();
+    a.x_scale = xscale;
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[prv];
@@ -623,6 +635,7 @@ int cr_solver::materialize() {
     if (!pend) return CR_OK;
     PassArgs a{};
     a.rev = next_sweep();
+    a.x_scale = xscale;
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[prv];
@@ -667,6 +680,7 @@ int cr_solver::step_adaptive() {
         const bool adv = defer && pend;
         PassArgs a{};
         a.rev = next_sweep();
+        a.x_scale = xscale;
         a.lam_h = lam_hi;
         a.lam_a = lam[cur];
         a.lam_b = lam[prv];
@@ -830,6 +844,7 @@ int cr_solver::step_once() {
     const double beta_k = opt.momentum ? (t - 1.0) / t_next : 0.0;
     PassArgs a{};
     a.rev = next_sweep();
+    a.x_scale = xscale;
     a.lam_h = lam_hi;
     a.lam_a = lam[cur];
     a.lam_b = lam[prv];
@@ -975,6 +990,7 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
         }
         PassArgs a{};
         a.rev = next_sweep();
+        a.x_scale = xscale;
         a.lam_h = lam_hi;
         a.lam_a = lam[cur];
         a.xhat = xhat64; a.xi = xic; a.yv = yc; a.dmy = dmyc;

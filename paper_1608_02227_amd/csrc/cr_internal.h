@@ -148,6 +148,7 @@ struct cr_solver {
     // lam is still the zero start: its stopping report is known in closed form (below)
     bool lam_zero = true;
     double yrange = 0.0;         // max ybar - min ybar
+    float xscale = 1.f;          // 2^-e with max |Xhat| (ones column included) in [2^(e-1), 2^e)
     int cur = 0;                 // buffer holding lam^k
     double t = 1.0;              // t_{k+1}
     double beta_last = 0.0;      // beta_k (0 before the first iteration)

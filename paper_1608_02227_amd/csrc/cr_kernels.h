@@ -122,6 +122,9 @@ struct PassArgs {
     // the direction from one multiplier sweep to the next, so that a sweep starts on the lines the
     // previous one touched last, which the last-level cache still holds)
     int rev;
+    // split trial passes: the power of two that scales the fit's locations (Xhat, ones column
+    // included) into [0.5, 1) for the FP16 residual
+    float x_scale;
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,

@@ -67,6 +67,33 @@ __device__ __forceinline__ void split_bf16_pair(float x0, float x1, uint32_t &hp
     lp = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{x0 - h0, x1 - h1}, b2));
 }
 
+// FP16 MFMA with K = 16: lane l holds A[l % 16][4 (l / 16) + q] and B[4 (l / 16) + q][l % 16],
+// q < 4, and receives C[4 (l / 16) + v][l % 16] (the output layout of the FP32 16x16x4 form).
+// (Only this K: a chain in which a K = 16 FP16 MFMA took a K = 32 one's result as its accumulator
+// gave wrong sums on this toolchain and device, and K = 16 alone is as fast here.)
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 mfma16_h16(h4 a, h4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+// x = hi + lo with hi = RNE(x) and lo = RNE(x - hi) in FP16: 22 significant bits, so for |x| < 1
+// the split holds x to 2^-24 (absolute; lo leaves FP16's normal range only for |x| < 2^-3, where
+// its absolute spacing is 2^-24).  Products of two splits are taken as hi*lo + lo*hi + hi*hi
+// (lo*lo ~ 2^-24 dropped), each exact in FP32 and accumulated in FP32: the FP32 MFMA's accuracy
+// relative to the operands' scale.
+__device__ __forceinline__ void split_f16(float x, _Float16 &hi, _Float16 &lo) {
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);
+}
+// 2^-e with 2^(e-1) <= m < 2^e (m > 0; 1 for m = 0), e clamped to [-40, 40]: scales a vector whose
+// largest magnitude is m into [0.5, 1) exactly.
+__device__ __forceinline__ float pow2_scale(float m) {
+    if (!(m > 0.f)) return 1.f;
+    int e;
+    (void)frexpf(m, &e);
+    e = e < -40 ? -40 : (e > 40 ? 40 : e);
+    return ldexpf(1.f, -e);
+}
+
 // ---- multiplier storage -------------------------------------------------------------------
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 // Round-to-nearest-even of a finite float to BF16.
@@ -179,6 +206,18 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     constexpr bool kBfAdj = kTrial && kSplit;
     constexpr int XTS = kSuper + 8;                  // BF16 transposed tile: row stride (elements)
     constexpr bool kResidual = (MODE != PASS_ADJ && MODE != PASS_REBASE);
+    // Split-form passes with a residual (the trial passes and the constant step's pass) form it on
+    // FP16 matrix cores: both operands scaled by powers of
+    // two into [0.5, 1) (each row of Xi by its largest entry, the locations by the fit's largest
+    // |Xhat|, PassArgs::x_scale) and split into hi + lo halves (split_f16), three products per pair
+    // of operands in K chunks of 16 -- the FP32 16x16x4 form's accuracy at under half of its matrix
+    // cycles.  The scales are exact: the accumulator starts at (y_j + d_i - y_i) c_i (c_i = row
+    // scale x location scale) and the step sizes are divided by c_i, so the epilogue's products
+    // s c_i * (1 / (s_a c_i)) equal the unscaled ones bit for bit.
+    constexpr bool kHalfRes = kSplit && kResidual && sizeof(T) == 4 && (kTrial || MODE == PASS_STEP);
+    constexpr bool kX32 = !kHalfRes || !kBfAdj;      // the FP32 location tile (FP32 adjoint MFMAs)
+    constexpr int HC16 = (4 * KS + 15) / 16;         // K = 16 chunks covering the residual's features
+    constexpr int XH = NP + 8;                       // FP16 tile row stride (halves; 16-byte rows)
     constexpr bool kColRed = kAdjoint || MODE == PASS_REPAIR;
     constexpr bool kReadA = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT || MODE == PASS_REBASE ||
                              kTrial);
@@ -187,7 +226,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     constexpr bool kLoads = kReadA || kReadB;
     typedef typename Vec4<T>::type V4;
 
-    __shared__ T sX[2 * BUF];
+    __shared__ T sX[kX32 ? 2 * BUF : 1];
+    // FP16 hi / lo splits of the scaled location tile (column-major: a column's features adjacent)
+    __shared__ __attribute__((aligned(16))) _Float16 sXH[kHalfRes ? 2 * kSuper * XH : 8];
+    __shared__ __attribute__((aligned(16))) _Float16 sXL[kHalfRes ? 2 * kSuper * XH : 8];
     __shared__ T sY[2 * kSuper];
     __shared__ T sYo[kAdv ? 2 * kSuper : 1];
     // transposed BF16 hi / lo copies of the staged Xhat tile (feature-major), for the BF16 adjoint
@@ -220,8 +262,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     // that the first exchange of the column-sum reduce-scatter needs no selects (every lane keeps
     // `out` and sends `out2`); their trial sums and adjoint accumulators are swapped back at the end.
     const bool cswap = kBfAdj && ((lr >> 3) & 1);
-    const T invA = cswap ? invL2 : invL, invB = cswap ? invL : invL2;
-    const T invLo = (T)a.inv_Lo;
+    T invA = cswap ? invL2 : invL, invB = cswap ? invL : invL2;
+    T invLo = (T)a.inv_Lo;
     const bool rebase_lam = (MODE == PASS_REBASE) && a.rebase_lam != 0;
     // Output rows of the 16x16x4 MFMA: lane group g, item v receives row 4 g + v in the FP32 form
     // and row 4 v + g in the FP64 form.  A-row rho is therefore fed the source that lane group
@@ -234,20 +276,57 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
 
     // Row-constant operands: B of the residual contraction is -Xi[i][4s + lq]; the accumulator
     // starts at y_j + d_i - y_i, so the product leaves s_ij itself (no separate subtraction).
-    T bxi[4 * MB];
+    T bxi[kHalfRes ? 1 : 4 * MB];
 #pragma unroll
-    for (int s = 0; s < 4 * MB; ++s)
-        bxi[s] = kResidual ? -xi[(size_t)i * NP + 4 * s + lq] : (T)0;
+    for (int s = 0; s < (kHalfRes ? 1 : 4 * MB); ++s)
+        bxi[s] = (kResidual && !kHalfRes) ? -xi[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmy_i = kResidual ? dmy[i] : (T)0;
     const T roff_i = (MODE == PASS_REPAIR && a.row_off) ? (T)a.row_off[i] : (T)0;
     // PASS_ADV: the previous trial's row operands (re-forming its accepted candidate)
     const T *xio = static_cast<const T *>(a.xi_o);
     const T *yvo = static_cast<const T *>(a.yv_o);
-    T bxio[kAdv ? 4 * MB : 1];
+    T bxio[kAdv && !kHalfRes ? 4 * MB : 1];
 #pragma unroll
-    for (int s = 0; s < (kAdv ? 4 * MB : 1); ++s)
-        bxio[s] = kAdv ? -xio[(size_t)i * NP + 4 * s + lq] : (T)0;
+    for (int s = 0; s < (kAdv && !kHalfRes ? 4 * MB : 1); ++s)
+        bxio[s] = (kAdv && !kHalfRes) ? -xio[(size_t)i * NP + 4 * s + lq] : (T)0;
     const T dmyo_i = kAdv ? static_cast<const T *>(a.dmy_o)[i] : (T)0;
+    // FP16 row operands: B[k][row lr] = -Xi[i][k] c, lane (lr, lq) holding features 16 c + 4 lq + q
+    // of chunk c; rsc / rsco = c_i of the new and of the previous trial's point
+    constexpr int H16 = kHalfRes ? HC16 : 1, O16 = kAdv ? H16 : 1;
+    h4 rh16[H16], rl16[H16], oh16[O16], ol16[O16];
+    T rsc = (T)1, rsco = (T)1;
+    if constexpr (kHalfRes) {
+        auto load_row = [&](const T *src, h4 *h16, h4 *l16) -> T {
+            float v16[H16][4];
+            float mx = 0.f;
+#pragma unroll
+            for (int c = 0; c < HC16; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    v16[c][q] = (float)src[(size_t)i * NP + 16 * c + 4 * lq + q];
+                    mx = fmaxf(mx, fabsf(v16[c][q]));
+                }
+            mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+            const float al = pow2_scale(mx);
+#pragma unroll
+            for (int c = 0; c < HC16; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    _Float16 hh, ll;
+                    split_f16(-v16[c][q] * al, hh, ll);
+                    h16[c][q] = hh;
+                    l16[c][q] = ll;
+                }
+            return (T)(al * a.x_scale);
+        };
+        rsc = load_row(xi, rh16, rl16);
+        if constexpr (kAdv) rsco = load_row(xio, oh16, ol16);
+        invA *= (T)1 / rsc;
+        invB *= (T)1 / rsc;
+        invLo *= (T)1 / rsco;
+    }
+    const T dmyc_i = dmy_i * rsc, dmyoc_i = dmyo_i * rsco;
 
     V4 acc[MB];
     V4 acc2[kTrial ? MB : 1];
@@ -289,7 +368,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
         for (int e = tid; e < kSuper * NP; e += NT) {
             const int jj = e / NP, m = e - jj * NP;
             const T v = xhat[(size_t)(c0 + jj) * NP + m];
-            sX[jj * SX + m] = v;
+            if constexpr (kHalfRes) split_f16((float)v * a.x_scale, sXH[jj * XH + m], sXL[jj * XH + m]);
+            if constexpr (kX32) sX[jj * SX + m] = v;
             if constexpr (kBfAdj) split_bf16((float)v, sXTh[m * XTS + jj], sXTl[m * XTS + jj]);
         }
         if (tid < kSuper) sY[tid] = kResidual ? yv[c0 + tid] : (T)0;
@@ -306,7 +386,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     for (int st = 0; st < nsup; ++st) {
         const int cst = sup_col(st);
         const int b = st & 1;
-        const T *sXb = sX + b * BUF;
+        const T *sXb = kX32 ? sX + b * BUF : sX;
         const T *sYb = sY + b * kSuper;
         const bool more = st + 1 < nsup;
 
@@ -344,6 +424,31 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
             for (int bb = 0; bb < NB; ++bb) {
                 // output item v of block bb is column jc + 4 bb + v of row i
                 const int jb = jc + 4 * bb;
+                if constexpr (kHalfRes) {
+                    // scaled start (y_j + d_i - y_i) c_i, one rounding as unscaled (c_i a power of 2)
+                    S[bb] = V4{fma(sYb[jb], rsc, dmyc_i), fma(sYb[jb + 1], rsc, dmyc_i), fma(sYb[jb + 2], rsc, dmyc_i),
+                               fma(sYb[jb + 3], rsc, dmyc_i)};
+                    if constexpr (kAdv)
+                        So[bb] = V4{fma(sYob[jb], rsco, dmyoc_i), fma(sYob[jb + 1], rsco, dmyoc_i),
+                                    fma(sYob[jb + 2], rsco, dmyoc_i), fma(sYob[jb + 3], rsco, dmyoc_i)};
+                    const _Float16 *ph = sXH + b * kSuper * XH + (jl + acol + 4 * bb) * XH;
+                    const _Float16 *pl = sXL + b * kSuper * XH + (jl + acol + 4 * bb) * XH;
+#pragma unroll
+                    for (int c = 0; c < HC16; ++c) {
+                        const int f0 = 16 * c + 4 * lq;
+                        const h4 ah = *reinterpret_cast<const h4 *>(ph + f0);
+                        const h4 al = *reinterpret_cast<const h4 *>(pl + f0);
+                        S[bb] = mfma16_h16(ah, rl16[c], S[bb]);
+                        S[bb] = mfma16_h16(al, rh16[c], S[bb]);
+                        S[bb] = mfma16_h16(ah, rh16[c], S[bb]);
+                        if constexpr (kAdv) {
+                            So[bb] = mfma16_h16(ah, ol16[c], So[bb]);
+                            So[bb] = mfma16_h16(al, oh16[c], So[bb]);
+                            So[bb] = mfma16_h16(ah, oh16[c], So[bb]);
+                        }
+                    }
+                    continue;
+                }
                 S[bb] = kResidual ? V4{sYb[jb] + dmy_i, sYb[jb + 1] + dmy_i, sYb[jb + 2] + dmy_i, sYb[jb + 3] + dmy_i}
                                   : V4{0, 0, 0, 0};
                 if (kAdv)
@@ -392,7 +497,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
                     const T H = (T)hi_at<REP>(cur, c);
                     const T l1 = (T)cur.a[c >> 2][c & 3], l2 = (T)cur.b[c >> 2][c & 3];
                     const T lt = l1 + bp * (l1 - l2);                    // low part of lam~^k
-                    T l0 = lt - s * invL;                                // Step 2 ...
+                    T l0 = lt - s * invA;                                // Step 2 ...
                     l0 = fmax(l0, -H);                                   // ... projected: H + l0 >= 0
                     l0 = ok ? l0 : (T)0;
                     cur.b[c >> 2][c & 3] = (float)l0;
@@ -657,12 +762,16 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
 
         // the next super tile's locations go to the other buffer
         if (more) {
-            T *sXn = sX + (b ^ 1) * BUF;
+            T *sXn = kX32 ? sX + (b ^ 1) * BUF : sX;
 #pragma unroll
             for (int q = 0; q < XR; ++q) {
                 const int e = tid + q * NT;
                 const int jj = e / NP, m = e - jj * NP;
-                sXn[jj * SX + m] = xr[q];
+                if constexpr (kHalfRes) {
+                    const int o = (b ^ 1) * kSuper * XH + jj * XH + m;
+                    split_f16((float)xr[q] * a.x_scale, sXH[o], sXL[o]);
+                }
+                if constexpr (kX32) sXn[jj * SX + m] = xr[q];
                 if constexpr (kBfAdj) {
                     const int o = (b ^ 1) * NP * XTS + m * XTS + jj;
                     split_bf16((float)xr[q], sXTh[o], sXTl[o]);
