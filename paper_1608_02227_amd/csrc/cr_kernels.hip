@@ -217,7 +217,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     constexpr bool kHalfRes = kSplit && kResidual && sizeof(T) == 4 && (kTrial || MODE == PASS_STEP);
     constexpr bool kX32 = !kHalfRes || !kBfAdj;      // the FP32 location tile (FP32 adjoint MFMAs)
     constexpr int HC16 = (4 * KS + 15) / 16;         // K = 16 chunks covering the residual's features
-    constexpr int XH = NP + 8;                       // FP16 tile row stride (halves; 16-byte rows)
+    constexpr int XH = NP + 4;                       // FP16 tile row stride (halves; 8-byte rows)
     constexpr bool kColRed = kAdjoint || MODE == PASS_REPAIR;
     constexpr bool kReadA = (MODE == PASS_STEP || MODE == PASS_ADJ || MODE == PASS_KKT || MODE == PASS_REBASE ||
                              kTrial);
