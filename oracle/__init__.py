@@ -16,6 +16,8 @@ Contents
            squares problem (Lawson-Hanson, via scipy) and the unregularized estimator of
            eq. ``original`` as a QP (SLSQP, via scipy).
 ``continuation``  the outer loop of Section 2.4.1 (gamma_t, delta_t -> 0 with warm starts).
+``blocks`` P-APG with K-block partial dualization (Section 2.1): only the pairs between blocks are
+           dualized, and Step 1 solves each block's QP exactly (NNLS on the block's dual).
 
 All arithmetic is float64 with numpy's default round-to-nearest.  Each function cites the
 passage of the paper (Aybat & Wang, "A Parallelizable Dual Smoothing Method for Large Scale

@@ -55,7 +55,17 @@ MUTATIONS = [
     ("continuation_weight", "continuation.py", "g_t = kappa_gamma * eps_t", "g_t = kappa_delta * eps_t"),
     ("exact_subgradient_sign", "exact.py", "l * n:(l + 1) * n] = -T @ x", "l * n:(l + 1) * n] = T @ x"),
     ("exact_t_block", "exact.py", "T[:, l] = -1.0", "T[:, l] = 1.0"),
+    # the K-block partial dualization (its own pins, test_oracle_blocks.py)
+    ("blocks_step_mask_dropped", "blocks.py", "th = np.maximum(0.0, th_tilde - s / L) * mask",
+     "th = np.maximum(0.0, th_tilde - s / L)"),
+    ("blocks_projection_rhs_sign", "blocks.py", "b = np.concatenate([-y0, -math.sqrt(gamma) * xi0.reshape(-1)])",
+     "b = np.concatenate([y0, -math.sqrt(gamma) * xi0.reshape(-1)])"),
+    ("blocks_projection_xi_scale", "blocks.py", "xi = xi0 + (A2.T @ mu / gamma).reshape(p, n)",
+     "xi = xi0 + (A2.T @ mu * gamma).reshape(p, n)"),
+    ("blocks_sigma_unmasked", "blocks.py", "z = pair_residual(x, vy, vxi) * mask", "z = pair_residual(x, vy, vxi)"),
+    ("blocks_partition_interleaved", "blocks.py", "return np.arange(N) // p", "return np.arange(N) % p"),
 ]
+BLOCK_PINS = ["test_oracle_blocks.py"]
 
 
 def _copy_tree(dst, mutation=None):
@@ -68,7 +78,7 @@ def _copy_tree(dst, mutation=None):
     os.makedirs(pkg)
     for f in ("__init__.py", "workloads.py"):
         shutil.copy(os.path.join(ROOT, "paper_1608_02227_amd", f), pkg)
-    for f in ["conftest.py", *PIN_TESTS]:
+    for f in ["conftest.py", *PIN_TESTS, *BLOCK_PINS]:
         shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(dst, "tests"))
     if mutation is not None:
         _, fname, old, new = mutation
@@ -79,12 +89,12 @@ def _copy_tree(dst, mutation=None):
             f.write(src.replace(old, new))
 
 
-def _run_pins(dst):
+def _run_pins(dst, pins):
     env = dict(os.environ)
     env["PYTHONPATH"] = dst
     env["OPENBLAS_NUM_THREADS"] = "2"
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not slow",
-                        *[os.path.join("tests", t) for t in PIN_TESTS]], cwd=dst, env=env,
+                        *[os.path.join("tests", t) for t in pins]], cwd=dst, env=env,
                        capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-2000:]
 
@@ -98,7 +108,9 @@ def outcomes(tmp_path_factory):
     def one(m):
         dst = str(tmp_path_factory.mktemp(m[0] if m else "unmodified") / "repo")
         _copy_tree(dst, m)
-        return _run_pins(dst)
+        # a planted mistake in the block oracle meets the block pins; the rest the method's pins
+        pins = PIN_TESTS + BLOCK_PINS if m is None else (BLOCK_PINS if m[1] == "blocks.py" else PIN_TESTS)
+        return _run_pins(dst, pins)
     cases = [None] + MUTATIONS
     with ThreadPoolExecutor(max_workers=6) as ex:
         res = list(ex.map(one, cases))
