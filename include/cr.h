@@ -104,6 +104,15 @@ typedef struct {
     int32_t keep_lambda;     /* serving (cr_submit): 1 keeps the request's final multipliers (N x N
                                 FP64, host) until they are collected through the lambda argument of
                                 cr_wait / cr_poll; 0 (default) drops them.  Ignored elsewhere. */
+    int32_t block_size;      /* 0 (default): every pair constraint dualized (each point its own
+                                block).  p in [2, 100]: K-block partial dualization (Section 2.1):
+                                contiguous blocks of p points (the last may be shorter; at least two
+                                blocks), only the pairs between blocks dualized, and Step 1 solving
+                                each block's QP (eq. "eq:step1-problem") by a primal-dual interior-
+                                point method on the device.  Needs CR_FP64 and the constant step
+                                (step_rule 0).  The returned multipliers are then theta (between
+                                blocks) plus the blocks' own multipliers (inside the blocks). */
+    int32_t reserved2;
     const double *lambda0;   /* optional N x N warm start lam^0 (its diagonal is ignored; entries
                                 must be finite and >= 0, else CR_EINVAL), in the memory of the call's
                                 other inputs: host for cr_fit / cr_fit_continuation / cr_submit (which

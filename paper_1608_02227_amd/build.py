@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcr.so")
-SOURCES = ["cr_kernels.hip", "cr_api.hip", "cr_serve.hip", "cr_noalloc.hip", "cr_batch.hip"]
+SOURCES = ["cr_kernels.hip", "cr_api.hip", "cr_serve.hip", "cr_noalloc.hip", "cr_batch.hip", "cr_blocks.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

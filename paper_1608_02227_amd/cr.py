@@ -44,6 +44,8 @@ class CROptions(C.Structure):
         ("reform_fp64", C.c_int32),
         ("center", C.c_int32),
         ("keep_lambda", C.c_int32),
+        ("block_size", C.c_int32),
+        ("reserved2", C.c_int32),
         ("lambda0", C.c_void_p),
     ]
 
@@ -215,6 +217,8 @@ class Options:
                                     # storing both candidates (32 B/pair, one FP64 contraction fewer)
     center: bool = True             # mixed modes: work in the frame x - mean(x) (results unchanged)
     keep_lambda: bool = False       # Server: keep each request's final multipliers for wait / poll
+    block_size: int = 0             # > 1: K-block partial dualization with blocks of this many points
+                                    # (FP64, constant step; Step 1 by an on-device interior-point method)
 
     def to_c(self) -> CROptions:
         o = CROptions()
@@ -239,6 +243,7 @@ class Options:
         o.reform_fp64 = 1 if self.reform_fp64 else 0
         o.center = 1 if self.center else 0
         o.keep_lambda = 1 if self.keep_lambda else 0
+        o.block_size = self.block_size
         return o
 
 

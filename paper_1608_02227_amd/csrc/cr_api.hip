@@ -224,6 +224,11 @@ static int validate(int64_t N, int64_t n, double delta, const cr_options *opt) {
         if (opt->check_rule < 0 || opt->check_rule > 1) return CR_EINVAL;
         if (opt->reform_fp64 < 0 || opt->reform_fp64 > 1) return CR_EINVAL;
         if (opt->center < 0 || opt->center > 1 || opt->keep_lambda < 0 || opt->keep_lambda > 1) return CR_EINVAL;
+        // K-block partial dualization: FP64, constant step, blocks of at most kMaxBlock points and
+        // at least two blocks
+        if (opt->block_size < 0 || opt->block_size > kMaxBlock) return CR_EINVAL;
+        if (opt->block_size > 1 &&
+            (opt->precision != CR_FP64 || opt->step_rule != 0 || N <= opt->block_size)) return CR_EINVAL;
     }
     return CR_OK;
 }
@@ -297,6 +302,11 @@ int cr_solver::allocate_state(int64_t N, int64_t n) {
             CR_ALLOC(dmyo32, nr * 4);
         }
     }
+    if (blk > 1) {
+        const size_t nblk = (size_t)(N + blk - 1) / blk;
+        CR_ALLOC(blk_ws, nblk * block_ws_doubles(blk, (int)n) * 8);
+        CR_ALLOC(blk_iters, nblk * 4);
+    }
     CR_ALLOC(in_x, (size_t)N * n * 8);
     CR_ALLOC(in_y, (size_t)N * 8);
     CR_ALLOC(in_mu, (size_t)n * 8);
@@ -320,6 +330,7 @@ void configure(cr_solver *s, int64_t N, int64_t n, const cr_options &opt) {
     s->adaptive = opt.step_rule == 1;
     s->upsilon = opt.upsilon;
     s->fp32pass = opt.precision != CR_FP64;
+    s->blk = opt.block_size > 1 ? opt.block_size : 0;
 }
 }  // namespace
 
@@ -518,6 +529,7 @@ int cr_solver::adjoint_to(int idx, double *y, double *xi, double *dmy, bool with
     a.xhat = xhat64;
     a.part_acc = part_acc;
     a.part_col = part_col;
+    a.blk = blk;   // under a partition: the dualized multipliers only (the blocks' own are ignored)
     CR_HIP(launch_pass(g, PASS_ADJ, false, rep, a, stream));
     FinalizeArgs f{};
     f.part_acc = part_acc;
@@ -598,6 +610,11 @@ int cr_solver::prime() {
         const double b = beta_last;
         CR_HIP(launch_lincomb(g, yc, xic, yr, xir, 1.0 + b, -b, 1.0 + b, -b, xhat64, y64, xi64, dmy64, y32, xi32,
                               dmy32, stream));
+    }
+    if (blk > 1) {
+        // Step 1 under the partition: the closed form of lam~ projected block by block
+        rc = project_blocks(y64, xi64, dmy64, false, nullptr);
+        if (rc) return rc;
     }
     primed = true;
     return CR_OK;
@@ -833,6 +850,28 @@ int cr_solver::step_adaptive() {
     return CR_OK;
 }
 
+// Step 1 under a K-block partition: the closed-form point in (y, xi) projected onto every block's
+// pair constraints (eq. "subgradient_split"), in place; with lam_out, the blocks' multipliers go to
+// the intra-block entries of that FP64 multiplier array.
+int cr_solver::project_blocks(double *y, double *xi, double *dmy, bool with_rowred, double *lam_out) {
+    BlockProjArgs b{};
+    b.xhat = xhat64;
+    b.y = y; b.xi = xi; b.dmy = dmy;
+    b.ybar = ybar64;
+    b.rowred = with_rowred ? rowred : nullptr;
+    b.lam = lam_out;
+    b.ld = g.ld;
+    b.ws = blk_ws;
+    b.ws_doubles = block_ws_doubles(blk, g.n);
+    b.iters = blk_iters;
+    b.delta = delta;
+    b.tol = 1e-11;
+    b.N = g.N; b.n = g.n; b.NP = g.NP; b.p = blk;
+    b.max_iter = 100;
+    CR_HIP(launch_block_project(g, b, stream));
+    return CR_OK;
+}
+
 int cr_solver::step_once() {
     test_fresh = false;
     lam_zero = false;
@@ -853,6 +892,7 @@ int cr_solver::step_once() {
     a.inv_L = 1.0 / L;
     a.part_acc = part_acc;
     a.part_col = part_col;
+    a.blk = blk;
     if (fp32pass) {
         a.xhat = xhat32; a.xi = xi32; a.yv = y32; a.dmy = dmy32;
     } else {
@@ -879,6 +919,11 @@ int cr_solver::step_once() {
     f.wbase = wbase;
     f.inv_delta = 1.0 / delta;
     CR_HIP(launch_finalize(g, fp32pass, f, stream));
+    if (blk > 1) {
+        // Step 1 of the next iteration: the closed form of lam~^{k+1}, projected block by block
+        const int rc = project_blocks(y64, xi64, dmy64, false, nullptr);
+        if (rc) return rc;
+    }
     std::swap(cur, prv);
     t = t_next;
     beta_last = beta_k;
@@ -943,6 +988,7 @@ int cr_solver::lipschitz(double *Lout, double *s2out, int32_t *itout) {
             a.xhat = xhat64; a.xi = xi64; a.yv = y64; a.dmy = dmy64;
         }
         a.part_acc = part_acc; a.part_col = part_col; a.part_red = part_red;
+        a.blk = blk;   // sigma_max of the dualized rows only
         CR_HIP(launch_pass(g, PASS_POWER, f32, REP_F64, a, stream));
         FinalizeArgs f{};
         f.part_acc = part_acc; f.part_col = part_col; f.xf = xhat64; f.ybar = ybar64;
@@ -986,6 +1032,13 @@ int cr_solver::check(cr_report *rep_out, bool certificate) {
         if (rc) return rc;
         if (!have_eta) {
             rc = adjoint_to(cur, yc, xic, dmyc, true, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+        }
+        if (blk > 1) {
+            // eta(lam^k) under the partition, and the blocks' multipliers into lam^k's intra-block
+            // entries: the test then reads the whole problem's multipliers, whose closed form is
+            // that projection
+            rc = project_blocks(yc, xic, dmyc, true, static_cast<double *>(lam[cur]));
             if (rc) return rc;
         }
         PassArgs a{};

@@ -95,6 +95,11 @@ struct cr_solver {
     void *part_acc2 = nullptr, *part_col2 = nullptr;
     double *block_part = nullptr;   // per-block sums of the trial finalize
     double *decision = nullptr;     // the trial reduction's step decision (device, 4 values)
+    // K-block partial dualization (options.block_size > 1): block size, the block IPM's workspace
+    // and its iteration counts per block
+    int blk = 0;
+    double *blk_ws = nullptr;
+    int *blk_iters = nullptr;
     unsigned timing_tick = 0;       // samples one in four trial launches for the pass timing
     double *uD[2] = {nullptr, nullptr}, *wD[2] = {nullptr, nullptr};
     double *ye[2] = {nullptr, nullptr}, *xie[2] = {nullptr, nullptr}, *dmye[2] = {nullptr, nullptr};
@@ -175,6 +180,7 @@ struct cr_solver {
     int refresh_eta(bool have_cur_in_yc);
     int materialize();
     int lambda_rows_via_scratch(double *lambda);
+    int project_blocks(double *y, double *xi, double *dmy, bool with_rowred, double *lam_out);
     int lipschitz(double *L, double *s2, int32_t *it);
     int check(cr_report *rep, bool certificate);
     int promote();

@@ -125,6 +125,9 @@ struct PassArgs {
     // split trial passes: the power of two that scales the fit's locations (Xhat, ones column
     // included) into [0.5, 1) for the FP16 residual
     float x_scale;
+    // > 1: K-block partial dualization with blocks of `blk` consecutive points; the pass treats the
+    // pairs inside a block like the diagonal (no multiplier, no contribution)
+    int blk;
 };
 
 hipError_t launch_pass(const Geometry &g, PassMode mode, bool fp32, LamRep rep,
@@ -192,6 +195,31 @@ hipError_t launch_accept(const Geometry &g, const double *yt, const double *xit,
                          const double *const uD[2], const double *const wD[2], const double *yk, const double *xik,
                          double *ye, double *xie, double *dmye, float *y32, float *xi32, float *dmy32,
                          const double *xhat64, double inv_delta, double beta, const double *decision, hipStream_t st);
+
+// ---- K-block partial dualization: Step 1's block QPs (cr_blocks.hip) -----------------------
+// Points per block at most (the IPM keeps a block's Schur complement and locations in LDS).
+constexpr int kMaxBlock = 100;
+// One launch projects the closed-form point of every block of p consecutive points (the last block
+// may be shorter) onto the block's pair constraints in the norm of diag(I, delta I), by a
+// primal-dual interior-point method per block (one workgroup each).  y, xi (padded rows, stride NP)
+// hold the closed-form point in and the projection out; dmy receives xi^T x - y; rowred (optional)
+// the rows' (y - ybar)^2 and ||xi||^2; lam (optional, leading dimension ld) the blocks' multipliers in
+// the intra-block entries; iters (optional, one int per block) the IPM iterations taken.
+struct BlockProjArgs {
+    const double *xhat;
+    double *y, *xi, *dmy;
+    const double *ybar;
+    double *rowred;
+    double *lam;
+    int ld;
+    double *ws;               // workspace: blocks x ws_doubles
+    size_t ws_doubles;        // block_ws_doubles(p, n)
+    int *iters;
+    double delta, tol;
+    int N, n, NP, p, max_iter;
+};
+size_t block_ws_doubles(int p, int n);
+hipError_t launch_block_project(const Geometry &g, const BlockProjArgs &a, hipStream_t st);
 
 // ---- grouped launches (serving: the same step of several small fits in one launch) ----------
 // Fit f of a group owns the launch's workgroups [off[f], off[f + 1]); its tiles, reductions and

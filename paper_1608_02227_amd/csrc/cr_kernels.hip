@@ -251,6 +251,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
     const int strip = bid / g.chunks;
     const int i = strip * kRows + w * 16 + lr;      // < Nr always
     const bool row_ok = i < g.N;
+    const int blk = a.blk > 1 ? a.blk : 1;          // pairs of one block are not dualized
+    const int iblk = i / blk;
     const int cbeg = chunk * g.chunk_cols;
     const int cend = min(g.ld, cbeg + g.chunk_cols);
     const int nsup = (cend - cbeg) / kSuper;
@@ -469,19 +471,21 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, const Geometry &g, 
             T out[CPL];
             T out2[kTrial ? CPL : 1];
             T cand_a[kTrial ? CPL : 1], cand_b[kTrial ? CPL : 1];
-            // Pair validity (i != j, both real points) only varies inside tiles that touch the
-            // diagonal or the padding; every other tile takes the unmasked path.  The branch is
+            // Pair validity (i != j, both real points, and under a K-block partition i and j in
+            // different blocks) only varies inside tiles that touch the diagonal (the diagonal
+            // blocks) or the padding; every other tile takes the unmasked path.  The branch is
             // uniform over the wave and holds no memory operation.
             const int i0w = strip * kRows + w * 16;
             const int jt0 = cst + jl;
-            const bool interior = (i0w + 16 <= g.N) && (jt0 + TW <= g.N) && (i0w + 16 <= jt0 || jt0 + TW <= i0w);
+            const bool interior = (i0w + 16 <= g.N) && (jt0 + TW <= g.N) &&
+                                  ((i0w + 15) / blk < jt0 / blk || (jt0 + TW - 1) / blk < i0w / blk);
             // split forms: trial sums of this tile in FP32, folded into the FP64 totals once per tile
             T tr0 = (T)0, tr1 = (T)0, tr2 = (T)0, tr3 = (T)0;
             auto epilogue = [&](auto masked) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int j = j0 + c;
-                const bool ok = masked ? (row_ok && (j < g.N) && (j != i)) : true;
+                const bool ok = masked ? (row_ok && (j < g.N) && (j != i) && (j / blk != iblk)) : true;
                 const T s = S[c >> 2][c & 3];                          // s_ij
                 if constexpr (MODE == PASS_STEP && REP == REP_F64) {
                     const T P = (T)cur.p[c], Q = (T)cur.q[c];

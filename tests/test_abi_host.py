@@ -62,7 +62,8 @@ def test_fit_rejects_bad_options_on_host(cr):
     for field, value in [("check_every", 0), ("precision", 7), ("L", -1.0), ("power_max_iters", 0),
                          ("step_rule", 2), ("upsilon", 1.0), ("upsilon", float("inf")), ("restart", 2),
                          ("power_rtol", -1.0), ("stop_rule", 2), ("check_rule", 2), ("check_rule", -1),
-                         ("center", 2), ("center", -1), ("keep_lambda", 2)]:
+                         ("center", 2), ("center", -1), ("keep_lambda", 2),
+                         ("block_size", 101), ("block_size", -1), ("block_size", 2)]:
         opt = cr.Options().to_c()
         setattr(opt, field, value)
         rc = lib.cr_fit(4, 2, cr._ptr(x), cr._ptr(yb), 1e-3, 1e-4, C.byref(opt), cr._ptr(y), cr._ptr(xi), None, None)

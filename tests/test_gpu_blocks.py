@@ -1,0 +1,122 @@
+"""K-block partial dualization on the GPU (Section 2.1; options.block_size) against the block oracle.
+
+The GPU solves every block's Step-1 QP with an interior-point method run to 1e-12 of the block's
+scale; the oracle solves the same QPs exactly (NNLS on their duals).  Iterates theta^k (the
+multipliers of the pairs between blocks) are compared elementwise with the oracle's run from the
+same L; sigma_max of the dualized rows against the oracle's power iteration; converged fits against
+the exact solution of the whole QP (the unique minimizer does not depend on the partition); the
+stopping report, taken on theta + the blocks' own multipliers, against the oracle's report of the
+same total multipliers."""
+import importlib
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+B = importlib.import_module("oracle.blocks")
+E = importlib.import_module("oracle.exact")
+P = importlib.import_module("oracle.papg")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return torch
+
+
+def _data(N, n, seed, noise=0.1):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, size=(N, n))
+    y = (x ** 2).sum(axis=1) + noise * rng.standard_normal(N)
+    return x, y
+
+
+def _opt(cr, p, **kw):
+    return cr.Options(precision="fp64", step_rule="constant", block_size=p, **kw)
+
+
+@pytest.mark.parametrize("N,n,p", [(48, 2, 12), (45, 3, 10), (40, 5, 8)])
+def test_block_iterates_match_oracle(cr, torch_dev, N, n, p):
+    x, y = _data(N, n, N + n)
+    g = 0.05
+    L = B.lipschitz_inter(x, g, p)[0]
+    ks = [1, 2, 5, 10, 25]
+    ref = []
+    B.papg_blocks(x, y, g, p, 0.0, L=L, max_iters=ks[-1], check_every=10 ** 6, iterates=ref)
+    ref = dict(ref)
+    print(f"block iterates N={N} n={n} p={p}", flush=True)
+    with cr.Solver(x, y, g, _opt(cr, p)) as s:
+        s.set_L(L)
+        done = 0
+        for k in ks:
+            s.iterate(k - done)
+            done = k
+            got = s.lam()
+            scale = max(np.abs(ref[k]).max(), 1e-300)
+            err = np.max(np.abs(got - ref[k])) / scale
+            print(f"  k={k}: {err:.2e}", flush=True)
+            assert err <= 1e-6, k
+            # the pairs inside a block carry no multiplier between tests
+            assert np.all(got[~B.inter_mask(N, p)] == 0.0)
+
+
+@pytest.mark.parametrize("N,n,p", [(48, 2, 12), (45, 3, 10)])
+def test_block_sigma_matches_oracle(cr, torch_dev, N, n, p):
+    x, y = _data(N, n, 3 * N)
+    g = 0.05
+    L_ref, s2_ref, _ = B.lipschitz_inter(x, g, p)
+    with cr.Solver(x, y, g, _opt(cr, p)) as s:
+        L, s2, _ = s.lipschitz()
+    assert s2 == pytest.approx(s2_ref, rel=1e-6)
+    assert L == pytest.approx(L_ref, rel=1e-6)
+    # fewer dualized rows than the full partition
+    assert s2 <= P.lipschitz(x, g)[1] * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("N,n,p", [(36, 2, 9), (33, 3, 10)])
+def test_converged_block_fit_reaches_the_exact_minimizer(cr, torch_dev, N, n, p):
+    x, y = _data(N, n, 7 * N)
+    g = 0.1
+    ref = E.exact_solve(x, y, g)
+    print(f"converged block fit N={N} n={n} p={p}", flush=True)
+    r = cr.fit(x, y, g, 1e-7, _opt(cr, p, check_every=25), allow_noconv=False, return_lambda=True)
+    assert r.report["kkt"] <= 1e-7
+    assert np.max(np.abs(r.y - ref["y"])) <= 1e-6 * np.abs(ref["y"]).max()
+    # the returned multipliers are those of the whole problem: theta between the blocks plus the
+    # blocks' own; their closed form is the returned primal point
+    u, w = P.pair_adjoint(x, r.lam)
+    np.testing.assert_allclose(r.y, y + u, atol=1e-8 * np.abs(y).max())
+    np.testing.assert_allclose(r.xi, w / g, atol=1e-7 * max(1.0, np.abs(r.xi).max()))
+    assert r.lam.min() >= 0.0
+
+
+def test_block_report_matches_oracle_report(cr, torch_dev):
+    N, n, p = 40, 2, 10
+    x, y = _data(N, n, 11)
+    g = 0.05
+    L = B.lipschitz_inter(x, g, p)[0]
+    ref = []
+    B.papg_blocks(x, y, g, p, 0.0, L=L, max_iters=60, check_every=10 ** 6, iterates=ref)
+    th = ref[-1][1]
+    _, _, mu = B.eta(x, y, g, th, p)
+    want = P.kkt_report(x, y, g, th + mu)
+    with cr.Solver(x, y, g, _opt(cr, p)) as s:
+        s.set_L(L)
+        s.iterate(60)
+        got = s.report()
+    for key in ["kkt", "max_viol", "comp_sum", "primal_obj", "dual_obj"]:
+        assert got[key] == pytest.approx(want[key], rel=1e-6, abs=1e-9), key
+
+
+def test_block_options_are_validated(cr, torch_dev):
+    x, y = _data(20, 2, 1)
+    for opt in [cr.Options(precision="mixed_fp32", step_rule="constant", block_size=5),
+                cr.Options(precision="fp64", step_rule="adaptive", block_size=5),
+                cr.Options(precision="fp64", step_rule="constant", block_size=20),
+                cr.Options(precision="fp64", step_rule="constant", block_size=101)]:
+        with pytest.raises(cr.CRError) as e:
+            cr.fit(x, y, 0.05, 1e-4, opt)
+        assert e.value.code == cr.CR_EINVAL
