@@ -867,7 +867,7 @@ int cr_solver::project_blocks(double *y, double *xi, double *dmy, bool with_rowr
     b.delta = delta;
     b.tol = 1e-11;
     b.N = g.N; b.n = g.n; b.NP = g.NP; b.p = blk;
-    b.max_iter = 100;
+    b.max_iter = 60;
     CR_HIP(launch_block_project(g, b, stream));
     return CR_OK;
 }

@@ -38,7 +38,7 @@ def _opt(cr, p, **kw):
     return cr.Options(precision="fp64", step_rule="constant", block_size=p, **kw)
 
 
-@pytest.mark.parametrize("N,n,p", [(48, 2, 12), (45, 3, 10), (40, 5, 8)])
+@pytest.mark.parametrize("N,n,p", [(48, 2, 12), (45, 3, 10), (40, 5, 8), (36, 20, 12), (30, 40, 10)])
 def test_block_iterates_match_oracle(cr, torch_dev, N, n, p):
     x, y = _data(N, n, N + n)
     g = 0.05

@@ -105,15 +105,18 @@ def outcomes(tmp_path_factory):
     (each is independent; together they take about a minute instead of three and a half)."""
     from concurrent.futures import ThreadPoolExecutor
 
-    def one(m):
-        dst = str(tmp_path_factory.mktemp(m[0] if m else "unmodified") / "repo")
+    def one(job):
+        m, dst = job
         _copy_tree(dst, m)
         # a planted mistake in the block oracle meets the block pins; the rest the method's pins
         pins = PIN_TESTS + BLOCK_PINS if m is None else (BLOCK_PINS if m[1] == "blocks.py" else PIN_TESTS)
         return _run_pins(dst, pins)
     cases = [None] + MUTATIONS
+    # the temporary folders are made here, one at a time (pytest's numbered folders are not safe to
+    # create from several threads at once)
+    jobs = [(m, str(tmp_path_factory.mktemp(m[0] if m else "unmodified") / "repo")) for m in cases]
     with ThreadPoolExecutor(max_workers=6) as ex:
-        res = list(ex.map(one, cases))
+        res = list(ex.map(one, jobs))
     return {("unmodified" if m is None else m[0]): r for m, r in zip(cases, res)}
 
 
