@@ -40,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FP64_PEAK_GFLOPS_PER_CU = 78.6e3 / 256   # MI355X FP64 vector (and matrix) peak over 256 CUs
 WORKLOAD = "quad_N8000_n40"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1608_02227_amd", "csrc", "cr_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_traffic_quad_N8000_n40.json")
@@ -163,9 +164,8 @@ def cpu_baseline(x, ybar, delta: float, L: float, iters: int, rule: str, restart
     # the oracle's loop ends with one stopping report; it is charged to the sample as well
     out = {"value": round(iters / dt, 4), "unit": "dual iterations/s", "cores": host["blas_threads"] or os.cpu_count(),
            "kind": "oracle",
-           "sample": f"first {iters} P-APG iterations ({rule} step{', restart' if restart else ''}, plus one "
-                     f"stopping report) of the same N={x.shape[0]}, n={x.shape[1]} fit, FP64 numpy oracle, "
-                     f"L fixed; {dt:.1f} s",
+           "sample": f"first {iters} iterations ({rule}{'+restart' if restart else ''}, one report) of the "
+                     f"N={x.shape[0]} n={x.shape[1]} fit, L fixed; {dt:.1f} s",
            "seconds_per_iter": round(dt / iters, 4), **host}
     if c1:
         wl1 = W.WORKLOADS["sqnorm_N200_n2"]
@@ -314,7 +314,7 @@ def _g4(v):
 # The driver keeps a bounded tail of stdout: the one JSON line must stay well inside it.
 LINE_LIMIT = 4000
 # optional sections, dropped last-first if the line would exceed LINE_LIMIT
-OPTIONAL_ORDER = ["other_seeds", "continuation", "large_fit", "configs", "serving", "compare"]
+OPTIONAL_ORDER = ["other_seeds", "kblock", "continuation", "large_fit", "configs", "serving", "compare"]
 
 
 def render_line(out: dict) -> str:
@@ -331,6 +331,73 @@ def render_line(out: dict) -> str:
             out["dropped_for_length"] = dropped
             line = json.dumps(out, separators=(",", ":"))
     return line
+
+
+def block_ipm_flops(q: int, n: int) -> int:
+    """Algorithmic FP64 flops of one interior-point iteration on one block of q points (two flops per
+    multiply-add): the Schur complement S = M00 - V^T V on its lower triangle, V = F_a^-1 M0a^T (q
+    columns per point), the M_aa blocks (sum_c d_ac x_c x_c^T), the per-point factors and S's
+    L D L^T, the two Newton solves' triangular solves, and the pair passes' n-vector products (lin,
+    three row-times-locations sums, the r0 and slack-step products)."""
+    tri = n * (n + 1) // 2
+    pairs = q * (q - 1)
+    return (q * (q + 1) // 2 * q * n * 2 + q * q * n * n + q * q * tri * 3 + q * n ** 3 // 3 + q ** 3 // 3
+            + 2 * (4 * q * n * n + 4 * q * q) + 6 * 2 * pairs * n)
+
+
+def run_kblock(cr, W, torch, iters: int, converge_tol: float = 0.0) -> dict:
+    """K-block partial dualization (Section 2.1) at the paper's block setting of Section 4 (blocks of
+    100 points, n = 20; N = 2400 is its largest, K = 24), on the paper-shaped quadratic generator:
+    FP64 constant-step P-APG, `iters` iterations timed after one warm-up, with the blocks and with
+    every pair dualized on the same input.  The block kernel's share of an iteration divided by the
+    interior-point iterations of the last Step 1 gives its time per IPM iteration, against the FP64
+    peak of the CUs it occupies (one workgroup per block).  With converge_tol > 0 (not in the
+    default run): both partitions fitted to that KKT tolerance at N = 800 (K = 8), iterations and
+    seconds."""
+    N, n, p, delta = 2400, 20, 100, 1e-3
+    x, yb = W.paper_shaped(N, n, "quadratic", 0)
+    per = {}
+    for bs in (p, 0):
+        opt = cr.Options(precision="fp64", step_rule="constant", block_size=bs)
+        with cr.Solver(x, yb, delta, opt) as s:
+            L = s.lipschitz()[0]
+            s.iterate(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.iterate(iters)
+            dt = time.perf_counter() - t0
+            its = s.block_iters() if bs else None
+        per[bs] = (1e3 * dt / iters, L, its)
+    (ms_b, L_b, its), (ms_a, L_a, _) = per[p], per[0]
+    ipm = float(its.mean())
+    us_ipm = 1e3 * (ms_b - ms_a) / ipm
+    fl = block_ipm_flops(p, n)
+    gf = fl / (us_ipm * 1e-6) / 1e9
+    log(f"k-block: L {L_b:.4g} with blocks, {L_a:.4g} with every pair dualized")
+    log(f"k-block: {ms_b:.2f} ms per iteration with blocks of {p} ({ipm:.1f} IPM iterations per block, "
+        f"{us_ipm:.0f} us each, {gf:.1f} GFLOP/s per CU), {ms_a:.4f} ms with every pair dualized")
+    out = {"workload": f"paper quadratic N={N} n={n}, blocks of {p}",
+           "ms_per_iter": [round(ms_b, 3), round(ms_a, 4)],
+           "ipm_iters": [round(ipm, 2), int(its.max())],
+           "roofline": {"bound": "alu", "achieved": round(gf, 2),
+                        "peak": round(FP64_PEAK_GFLOPS_PER_CU, 1), "unit": "GFLOP/s/CU fp64",
+                        "frac": round(gf / FP64_PEAK_GFLOPS_PER_CU, 4), "busy_cus": -(-N // p),
+                        "us_per_ipm_iter": round(us_ipm, 1)}}
+    if converge_tol > 0:
+        Nc = 800
+        xc, ybc = W.paper_shaped(Nc, n, "quadratic", 0)
+        conv = {"N": Nc, "tol": converge_tol}
+        for bs, key in ((p, "blocks"), (0, "all_pairs")):
+            opt = cr.Options(precision="fp64", step_rule="constant", block_size=bs, max_iters=200000,
+                             time_budget_s=300.0)
+            cr.fit(xc[:200], ybc[:200], delta, 1e-2, opt)      # warm-up (allocation, code paths)
+            t0 = time.perf_counter()
+            r = cr.fit(xc, ybc, delta, converge_tol, opt)
+            conv[key] = {"status": r.status, "iters": r.report["iters"], "s": round(time.perf_counter() - t0, 3),
+                         "kkt": _g4(r.report["kkt"])}
+            log(f"k-block convergence N={Nc}: {key} {r.report['iters']} iterations in {conv[key]['s']} s")
+        out["converge"] = conv
+    return out
 
 
 def run_probe(torch, cr, N: int, n: int, iters: int) -> dict:
@@ -413,6 +480,12 @@ def main() -> int:
                     help="also fit the N=40000, n=20 workload to tol, at most K iterations (0: skip)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the N=200 and N=2000 configurations (FP64 and mixed, to tolerance)")
+    ap.add_argument("--kblock", type=int, default=5, metavar="K",
+                    help="P-APG iterations timed for the K-block partial dualization leg (0 skips it)")
+    ap.add_argument("--kblock-only", action="store_true",
+                    help="run only the K-block leg and print it as one JSON line")
+    ap.add_argument("--kblock-converge", type=float, default=0.0, metavar="TOL",
+                    help="with --kblock-only: also fit both partitions to this KKT tolerance at N=800")
     ap.add_argument("--probe", type=int, default=0, metavar="N",
                     help="only run the memory probes at the pass geometry of an N-point, n=40 fit and print "
                          "their JSON line (no fits)")
@@ -437,6 +510,10 @@ def main() -> int:
     cr.load()
     if args.probe > 0:
         print(json.dumps({"probe": run_probe(torch, cr, args.probe, 40, 20)}), flush=True)
+        return 0
+    if args.kblock_only:
+        print(json.dumps({"kblock": run_kblock(cr, W, torch, max(args.kblock, 1), args.kblock_converge)},
+                         separators=(",", ":")), flush=True)
         return 0
     dev = torch.device("cuda:0")
     wl = W.WORKLOADS[WORKLOAD]
@@ -616,7 +693,7 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64", "fp64": "f64"}[args.precision],
-        "data": "synthetic (seeded; the named workload's shapes and distributions)",
+        "data": "synthetic (seeded, the workload's shapes)",
         "config": {"workload": f"{WORKLOAD}: x~U[-1,1]^40, f0=x'Qx, Q=M'M/40, eps~N(0,0.5^2)",
                    "N": wl.N, "n": wl.n, "delta": wl.delta, "tol": args.tol, "precision": args.precision,
                    "step_rule": rule, "momentum_restart": restart,
@@ -632,6 +709,8 @@ def main() -> int:
         out["configs"] = run_configs(cr, W, torch, rule, restart)
     if args.large > 0:
         out["large_fit"] = run_large(cr, W, args.large, args.tol, args.precision, rule, restart)
+    if args.kblock > 0:
+        out["kblock"] = run_kblock(cr, W, torch, args.kblock)
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations at N={wl.N} ...")
         out["cpu_baseline"] = cpu_baseline(x_h, yb_h, wl.delta, last["L"], args.cpu_iters, rule, restart)
@@ -640,8 +719,8 @@ def main() -> int:
         out["compare"] = compare
     if other_seeds:
         out["other_seeds"] = other_seeds
-    out["paper_context"] = ("none for this variant/workload; paper's largest (PAPG_A, K=N/100 MOSEK sub-QPs, "
-                            "MATLAB FP64, 24 cores): N=2400 n=80 897 s quad, 774 s exp")
+    out["paper_context"] = ("paper's largest (PAPG_A, K=N/100 MOSEK sub-QPs, 24 cores): "
+                            "N=2400 n=80 897 s quad, 774 s exp")
     print(render_line(out), flush=True)
     return 0
 

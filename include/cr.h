@@ -317,6 +317,12 @@ int cr_solver_get_lambda_rows(cr_solver *s, int64_t row0, int64_t nrows, double 
 int cr_solver_get_primal(cr_solver *s, double *y, double *xi);
 /* FP64 stopping report of lam^k (and the certificate if opt.certificate). */
 int cr_solver_report(cr_solver *s, cr_report *rep);
+/* K-block partial dualization (options.block_size = p > 1; Section 2.1, Step 1 split into the
+ * blocks' QPs of eq. "subgradient_split"): *nblocks = ceil(N / p) (0 with every pair dualized), and,
+ * when iters is not NULL, the interior-point iterations each block's QP took in the most recent
+ * Step 1 (0 before the first), copied to the host array iters[0 .. *nblocks) after the solver's
+ * stream has drained.  cap < *nblocks with iters given: CR_EINVAL. */
+int cr_solver_block_iters(cr_solver *s, int32_t *iters, int64_t cap, int64_t *nblocks);
 
 /* Tiling of the pair sweep for an N-point, n-feature fit on `device` (diagnostics and memory
  * probes): padded rows (= the multiplier arrays' leading dimension), column chunks per 128-row

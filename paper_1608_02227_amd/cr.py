@@ -154,6 +154,7 @@ def load() -> C.CDLL:
         "cr_solver_get_lambda": (C.c_int, [vp, vp]),
         "cr_solver_get_lambda_rows": (C.c_int, [vp, i64, i64, vp]),
         "cr_solver_get_primal": (C.c_int, [vp, vp, vp]),
+        "cr_solver_block_iters": (C.c_int, [vp, _P(i32), i64, _P(i64)]),
         "cr_solver_report": (C.c_int, [vp, _P(CRReport)]),
         "cr_op_residual": (C.c_int, [i64, i64, vp, vp, vp, vp, C.c_int]),
         "cr_op_adjoint": (C.c_int, [i64, i64, vp, vp, vp, vp, C.c_int]),
@@ -428,6 +429,18 @@ class Solver:
     def lam_rows(self, row0: int, nrows: int) -> np.ndarray:
         out = np.empty((nrows, self.N))
         _check(load().cr_solver_get_lambda_rows(self._h, row0, nrows, _ptr(out)), "get_lambda_rows")
+        return out
+
+    def block_iters(self) -> np.ndarray | None:
+        """Interior-point iterations of each block's QP in the most recent Step 1 (K-block mode),
+        else None."""
+        nb = C.c_int64()
+        _check(load().cr_solver_block_iters(self._h, None, 0, C.byref(nb)), "block_iters")
+        if nb.value == 0:
+            return None
+        out = np.zeros(nb.value, dtype=np.int32)
+        _check(load().cr_solver_block_iters(self._h, out.ctypes.data_as(C.POINTER(C.c_int32)), nb.value, C.byref(nb)),
+               "block_iters")
         return out
 
     def primal(self) -> tuple[np.ndarray, np.ndarray]:

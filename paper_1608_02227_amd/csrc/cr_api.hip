@@ -306,6 +306,7 @@ int cr_solver::allocate_state(int64_t N, int64_t n) {
         const size_t nblk = (size_t)(N + blk - 1) / blk;
         CR_ALLOC(blk_ws, nblk * block_ws_doubles(blk, (int)n) * 8);
         CR_ALLOC(blk_iters, nblk * 4);
+        if (hipMemset(blk_iters, 0, nblk * 4) != hipSuccess) return CR_EDEVICE;   // no Step 1 yet
     }
     CR_ALLOC(in_x, (size_t)N * n * 8);
     CR_ALLOC(in_y, (size_t)N * 8);
@@ -1450,6 +1451,18 @@ extern "C" int cr_solver_get_primal(cr_solver *s, double *y, double *xi) {
     rc = s->adjoint_to(s->cur, s->yc, s->xic, s->dmyc, false, nullptr, nullptr, nullptr);
     if (rc) return rc;
     return primal_out(s, s->yc, s->xic, y, xi, false);
+}
+
+extern "C" int cr_solver_block_iters(cr_solver *s, int32_t *iters, int64_t cap, int64_t *nblocks) {
+    if (!s || !nblocks) return CR_EINVAL;
+    const int64_t nb = s->blk > 1 ? (s->g.N + s->blk - 1) / s->blk : 0;
+    *nblocks = nb;
+    if (nb == 0 || !iters) return CR_OK;
+    if (cap < nb) return CR_EINVAL;
+    CR_HIP(hipSetDevice(s->device));
+    CR_HIP(hipStreamSynchronize(s->stream));
+    CR_HIP(hipMemcpy(iters, s->blk_iters, (size_t)nb * 4, hipMemcpyDeviceToHost));
+    return CR_OK;
 }
 
 extern "C" int cr_solver_report(cr_solver *s, cr_report *rep) {
