@@ -306,7 +306,8 @@ int cr_solver::allocate_state(int64_t N, int64_t n) {
         const size_t nblk = (size_t)(N + blk - 1) / blk;
         CR_ALLOC(blk_ws, nblk * block_ws_doubles(blk, (int)n) * 8);
         CR_ALLOC(blk_iters, nblk * 4);
-        if (hipMemset(blk_iters, 0, nblk * 4) != hipSuccess) return CR_EDEVICE;   // no Step 1 yet
+        // no Step 1 yet (a workspace is cleared by a fill kernel at the start of each fit instead)
+        if (!ws && hipMemset(blk_iters, 0, nblk * 4) != hipSuccess) return CR_EDEVICE;
     }
     CR_ALLOC(in_x, (size_t)N * n * 8);
     CR_ALLOC(in_y, (size_t)N * 8);

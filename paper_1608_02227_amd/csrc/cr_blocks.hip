@@ -22,8 +22,10 @@
 //  * the residuals r_p, r_d and the slack steps keep the difference form x_a - x_c; the Newton
 //    matrix blocks M_aa use the expanded form sum_c d_ac x_c x_c^T - D_a x_a x_a^T + x_a g_a^T +
 //    g_a x_a^T on locations centred on the block's mean (they only shape the direction);
-//  * each M_aa is factored, and every triangular solve with it run, by one thread with the vector in
-//    registers (n <= NB, a compile-time bound);
+//  * each M_aa is factored, and every single-vector triangular solve with it run, by one thread with
+//    the vector in registers (n <= NB, a compile-time bound): the points' dependent chains run side
+//    by side; V_a's q columns take one wave per point, one lane per column, with the factor in the
+//    wave's LDS buffer when it fits (n <= 27);
 //  * S = M00 - V^T V (V = stacked F_a^-1 M0a^T, q n x q) runs as a register-tiled product (4 x 4
 //    tiles of the lower triangle, the q n rows split in three), V staged through LDS;
 //  * S is factored as L D L^T in LDS with one barrier per column; the two triangular solves with it
@@ -120,6 +122,15 @@ __device__ __forceinline__ BlockWs carve(double *W, int q, int n) {
     return w;
 }
 
+// Packed lower-triangle index and its inverse (row of entry e).
+__device__ __forceinline__ int tix(int i, int j) { return i * (i + 1) / 2 + j; }
+__device__ __forceinline__ int tri_row(int e) {
+    int i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    while (i * (i + 1) / 2 > e) --i;
+    return i;
+}
+
 // z <- F^-T F^-1 z for one point's factor (n <= NB; entries of z beyond n are zero).
 template <int NB>
 __device__ __forceinline__ void factor_solve(const double *F, const double *fd, int n, double (&z)[NB]) {
@@ -175,6 +186,9 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
     // lanes (gq, gm) for sums over c of an n-vector: group gq takes c = gq, gq + G, ...
     const int G = 64 / n, gq = ln / n, gm = ln - gq * n;
     const int tri = n * (n + 1) / 2;
+    // a point's packed factor fits a wave's buffer (n <= 27): V reads it from LDS
+    const bool fl = tri <= kWB;
+    double *wF = rb1;
 
     // eta0 in; the locations centred on the block's mean (differences x_a - x_c are unchanged)
     for (int m = t; m < n; m += kBT) {
@@ -354,8 +368,10 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
         }
         if (phi <= 1.0 || mu < 1e-4 * tol_mu) break;
 
-        // --- factor each M_aa (one thread per point, the current row in registers) and, beside it,
-        // M00's lower triangle in place of d: -(d_ac + d_ca) off the diagonal
+        // --- factor each M_aa (one thread per point, the current row in registers, earlier rows from
+        // the workspace), then V_a[:, c] = F_a^-1 (M0a^T)[:, c] (d_ac (x_a - x_c) for c != a, -g_a for
+        // c = a): one wave per point, one lane per column with the column in registers, the factor
+        // read from the wave's LDS buffer when it fits there (n <= 27), else from the workspace
         for (int a = t; a < q; a += kBT) {
             double *F = w.F + (size_t)a * n * n;
             double *fd = w.fd + (size_t)a * n;
@@ -385,36 +401,57 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
                 fd[i] = 1.0 / piv;
             }
         }
-        for (int a = wid; a < q; a += kWaves)
-            for (int c = ln; c <= a; c += 64)
-                sS[a * ld + c] = (c == a) ? sFl[a] : -(sS[a * ld + c] + sS[c * ld + a]);
         __syncthreads();
-
-        // --- V_a[:, c] = F_a^-1 (M0a^T)[:, c]: d_ac (x_a - x_c) for c != a, -g_a for c = a
         for (int a = wid; a < q; a += kWaves) {
             const double *__restrict__ F = w.F + (size_t)a * n * n;
             const double *__restrict__ fd = w.fd + (size_t)a * n;
+            if (fl) {
+                // packed factor with 1 / L_kk on the diagonal
+                for (int e = ln; e < tri; e += 64) {
+                    const int i = tri_row(e), j = e - tix(i, 0);
+                    wF[e] = (i == j) ? fd[i] : F[i * n + j];
+                }
+                wave_sync();
+            }
             for (int s = 0; s < 2; ++s) {
                 const int c = ln + 64 * s;
                 if (c >= q) continue;
                 const double dac = (c == a) ? 0.0 : w.dd[(size_t)a * q + c];
                 double v[NB];
+                if (fl) {
 #pragma unroll
-                for (int m = 0; m < NB; ++m) {
-                    v[m] = 0.0;
-                    if (m < n) {
-                        double r = (c == a) ? -w.gv[a * n + m] : dac * (sX[a * XS + m] - sX[c * XS + m]);
+                    for (int m = 0; m < NB; ++m) {
+                        v[m] = 0.0;
+                        if (m < n) {
+                            double r = (c == a) ? -w.gv[a * n + m] : dac * (sX[a * XS + m] - sX[c * XS + m]);
 #pragma unroll
-                        for (int j = 0; j < m; ++j) r -= F[m * n + j] * v[j];
-                        v[m] = r * fd[m];
+                            for (int j = 0; j < m; ++j) r -= wF[tix(m, j)] * v[j];
+                            v[m] = r * wF[tix(m, m)];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < NB; ++m) {
+                        v[m] = 0.0;
+                        if (m < n) {
+                            double r = (c == a) ? -w.gv[a * n + m] : dac * (sX[a * XS + m] - sX[c * XS + m]);
+#pragma unroll
+                            for (int j = 0; j < m; ++j) r -= F[m * n + j] * v[j];
+                            v[m] = r * fd[m];
+                        }
                     }
                 }
-                // stores after the substitution, so that no store stands between F's loads
+                // stores after the substitution, so that no store stands between the factor's loads
 #pragma unroll
                 for (int m = 0; m < NB; ++m)
                     if (m < n) w.V[(size_t)(a * n + m) * q + c] = v[m];
             }
+            wave_sync();
         }
+        // M00's lower triangle in place of d: -(d_ac + d_ca) off the diagonal
+        for (int a = wid; a < q; a += kWaves)
+            for (int c = ln; c <= a; c += 64)
+                sS[a * ld + c] = (c == a) ? sFl[a] : -(sS[a * ld + c] + sS[c * ld + a]);
         __syncthreads();
 
         // --- S = M00 - V^T V on the lower triangle: 4 x 4 tiles, the rows of V in kKS groups
@@ -563,7 +600,7 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
                 wave_sync();
             }
             colsum(c0, c1, [&](int c, double cs) { sBy[c] = -w.ry[c] + (cs - sRt[c]); });
-            // z_a = M_aa^-1 b_a (one thread per point)
+            // z_a = M_aa^-1 b_a (one thread per point: the points' dependent chains run side by side)
             for (int a = t; a < q; a += kBT) {
                 double z[NB];
 #pragma unroll
