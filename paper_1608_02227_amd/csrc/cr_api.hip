@@ -870,7 +870,9 @@ int cr_solver::project_blocks(double *y, double *xi, double *dmy, bool with_rowr
     b.tol = 1e-11;
     b.N = g.N; b.n = g.n; b.NP = g.NP; b.p = blk;
     b.max_iter = 60;
+    b.warm = blk_warm ? 1 : 0;
     CR_HIP(launch_block_project(g, b, stream));
+    blk_warm = true;
     return CR_OK;
 }
 

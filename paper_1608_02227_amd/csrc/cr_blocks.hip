@@ -249,7 +249,9 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
         __syncthreads();
     };
 
-    // starting point: eta = eta0, s = max(A eta0, 1), theta = 1
+    // starting point: eta = eta0 and, cold, s = max(A eta0, 1), theta = 1; warm (A.warm: the
+    // workspace holds the slacks and multipliers the previous Step 1 ended on, for a nearby
+    // projection), both lifted to at least 1e-4 of the block's scale
     double ysc = 0.0;
     for (int e = t; e < q; e += kBT) ysc = fmax(ysc, fabs(w.y0[e]));
     for (int a = wid; a < q; a += kWaves) {
@@ -263,12 +265,25 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
             if (c == a) { w.sl[e] = 1.0; w.th[e] = 0.0; continue; }
             const double v = lin(a, c, ya);
             ysc = fmax(ysc, fabs(v));
-            w.sl[e] = fmax(v, 1.0);
-            w.th[e] = 1.0;
+            if (!A.warm) {
+                w.sl[e] = fmax(v, 1.0);
+                w.th[e] = 1.0;
+            }
         }
         wave_sync();
     }
     const double scale = 1.0 + wg_max(ysc, sh);
+    if (A.warm) {
+        const double lift = 1e-4 * scale;
+        for (int a = wid; a < q; a += kWaves)
+            for (int c = ln; c < q; c += 64) {
+                if (c == a) continue;
+                const size_t e = (size_t)a * q + c;
+                w.sl[e] = fmax(w.sl[e], lift);
+                w.th[e] = fmax(w.th[e], lift);
+            }
+        __syncthreads();
+    }
     const double tol = A.tol * scale;
     // complementarity target: a weakly active constraint (zero slack and zero multiplier at the
     // solution) keeps both near sqrt(mu), and the projection's error follows them; mu is driven

@@ -100,6 +100,7 @@ struct cr_solver {
     int blk = 0;
     double *blk_ws = nullptr;
     int *blk_iters = nullptr;
+    bool blk_warm = false;          // a Step 1 has run: its slacks and multipliers start the next
     unsigned timing_tick = 0;       // samples one in four trial launches for the pass timing
     double *uD[2] = {nullptr, nullptr}, *wD[2] = {nullptr, nullptr};
     double *ye[2] = {nullptr, nullptr}, *xie[2] = {nullptr, nullptr}, *dmye[2] = {nullptr, nullptr};

@@ -217,6 +217,7 @@ struct BlockProjArgs {
     int *iters;
     double delta, tol;
     int N, n, NP, p, max_iter;
+    int warm;                 // the workspace holds the previous Step 1's slacks and multipliers
 };
 size_t block_ws_doubles(int p, int n);
 hipError_t launch_block_project(const Geometry &g, const BlockProjArgs &a, hipStream_t st);
