@@ -19,6 +19,7 @@
 // Work split (512 threads, 8 waves, one block of q <= 100 points per workgroup):
 //  * pair passes run one row a per wave at a time, lanes over the partners c; sums over c of an
 //    n-vector (the xi parts of r_d, A^T w and M0a^T dy) split the lanes into 64 / n groups of n;
+//    the M_aa sums take 4 rows per wave (d transposed in LDS) so that each x_c x_c^T entry serves four;
 //  * the residuals r_p, r_d and the slack steps keep the difference form x_a - x_c; the Newton
 //    matrix blocks M_aa use the expanded form sum_c d_ac x_c x_c^T - D_a x_a x_a^T + x_a g_a^T +
 //    g_a x_a^T on locations centred on the block's mean (they only shape the direction);
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
 
     int it = 0;
     for (; it < A.max_iter && q > 1; ++it) {
-        // --- residuals: r_p = A eta - s, d = theta / s, mu; r_d = G eta + c - A^T theta; g_a; M_aa
+        // --- residuals: r_p = A eta - s, d = theta / s, mu; r_d = G eta + c - A^T theta; g_a
         double rpmax = 0.0, gap = 0.0, rdmax = 0.0;
         double cth0 = 0.0, cth1 = 0.0, cdd0 = 0.0, cdd1 = 0.0;
         for (int a = wid; a < q; a += kWaves) {
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
                     dv = thv / slv;
                     w.dd[e] = dv;
                 }
-                if (c < q) { rb1[c] = thv; rb2[c] = dv; sS[a * ld + c] = dv; }
+                if (c < q) { rb1[c] = thv; rb2[c] = dv; sS[c * ld + a] = dv; }   // d transposed in LDS
                 if (s == 0) { cth0 += thv; cdd0 += dv; } else { cth1 += thv; cdd1 += dv; }
                 rth += thv;
                 rdd += dv;
@@ -335,25 +336,6 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
                 w.rxi[e] = r;
                 rdmax = fmax(rdmax, fabs(r));
                 w.gv[e] = s2;
-                rbp[ln] = s2;
-            }
-            wave_sync();
-            // M_aa = delta I + sum_c d_ac x_c x_c^T - D_a x_a x_a^T + x_a g_a^T + g_a x_a^T
-            for (int e0 = 0; e0 < tri; e0 += 64) {
-                const int e = e0 + ln;
-                if (e < tri) {
-                    int m1 = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
-                    while ((m1 + 1) * (m1 + 2) / 2 <= e) ++m1;
-                    while (m1 * (m1 + 1) / 2 > e) --m1;
-                    const int m2 = e - m1 * (m1 + 1) / 2;
-                    double acc = 0.0;
-#pragma unroll 8
-                    for (int c = 0; c < q; ++c) acc += rb2[c] * (sX[c * XS + m1] * sX[c * XS + m2]);
-                    const double xa1 = sX[a * XS + m1], xa2 = sX[a * XS + m2];
-                    double v = acc - rdd * xa1 * xa2 + xa1 * rbp[m2] + rbp[m1] * xa2;
-                    if (m1 == m2) v += delta;
-                    w.F[(size_t)a * n * n + m1 * n + m2] = v;
-                }
             }
             if (ln == 0) { sRt[a] = rth; sRd[a] = rdd; }
             wave_sync();
@@ -382,6 +364,40 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
             for (int e = t; e < q * n; e += kBT) w.kxi[e] = w.xi[e];
         }
         if (phi <= 1.0 || mu < 1e-4 * tol_mu) break;
+
+        // --- M_aa = delta I + sum_c d_ac x_c x_c^T - D_a x_a x_a^T + x_a g_a^T + g_a x_a^T (the expanded
+        // form of sum_c d_ac (x_a - x_c)(x_a - x_c)^T): a wave takes 4 rows and 64 entries (m1 >= m2),
+        // so that one product x_c[m1] x_c[m2] serves four rows; d is read transposed from LDS
+        {
+            const int nrg = (q + 3) >> 2, nch = (tri + 63) >> 6;
+            for (int task = wid; task < nrg * nch; task += kWaves) {
+                const int rg = task / nch, ch = task - rg * nch;
+                const int e = ch * 64 + ln;
+                const int m1 = e < tri ? tri_row(e) : 0, m2 = e < tri ? e - tix(m1, 0) : 0;
+                int ar[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ar[r] = min(4 * rg + r, q - 1);
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+                for (int c = 0; c < q; ++c) {
+                    const double z = sX[c * XS + m1] * sX[c * XS + m2];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r] += sS[c * ld + ar[r]] * z;
+                }
+                if (e < tri) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int a = 4 * rg + r;
+                        if (a >= q) break;
+                        const double xa1 = sX[a * XS + m1], xa2 = sX[a * XS + m2];
+                        double v = acc[r] - sRd[a] * xa1 * xa2 + xa1 * w.gv[a * n + m2] + w.gv[a * n + m1] * xa2;
+                        if (m1 == m2) v += delta;
+                        w.F[(size_t)a * n * n + m1 * n + m2] = v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
 
         // --- factor each M_aa (one thread per point, the current row in registers, earlier rows from
         // the workspace), then V_a[:, c] = F_a^-1 (M0a^T)[:, c] (d_ac (x_a - x_c) for c != a, -g_a for
