@@ -43,12 +43,15 @@ namespace {
 constexpr int kBT = 512;                  // threads per workgroup
 constexpr int kWaves = kBT / 64;          // 8
 constexpr int kWB = 384;                  // per-wave LDS buffer: two q-rows (128 each) + two 64-vectors
-constexpr int kKC = 24;                   // rows of V per LDS stage of the Schur-complement product
-constexpr int kKS = 3;                    // row groups of a stage (kKC / kKS rows each)
-constexpr int kScr = kWaves * kWB;        // shared scratch (row buffers / column partials / V stage)
-constexpr int kPre = (kKC * kMaxBlock + kBT - 1) / kBT;
+constexpr int kKS = 3;                    // row groups of a stage of the Schur-complement product
+// rows of V per LDS stage of that product: 48 while the block's LDS leaves room (n <= 32), else 24
+constexpr int stage_rows(int NB) { return NB <= 32 ? 48 : 24; }
+// shared scratch (row buffers / column partials / V stage)
+constexpr int scratch_doubles(int NB) {
+    return stage_rows(NB) * kMaxBlock > kWaves * kWB ? stage_rows(NB) * kMaxBlock : kWaves * kWB;
+}
 constexpr int kLE = (kMaxBlock * (kMaxBlock + 1) / 2 + kBT - 1) / kBT;   // lower-triangle entries per thread
-static_assert(kKC * kMaxBlock <= kScr && 2 * kWaves * kMaxBlock <= kScr, "scratch too small");
+static_assert(2 * kWaves * kMaxBlock <= kWaves * kWB, "scratch too small");
 static_assert(kMaxBlock <= 128, "two partner slots per lane");
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -168,6 +171,9 @@ namespace {
 template <int NB>
 __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
     constexpr int XS = NB + 1;                                    // odd row stride of the locations
+    constexpr int kKC = stage_rows(NB), kScr = scratch_doubles(NB);
+    constexpr int kPre = (kKC * kMaxBlock + kBT - 1) / kBT;
+    static_assert(kKC % kKS == 0, "stage rows split into kKS groups");
     __shared__ double sS[kMaxBlock * (kMaxBlock + 1)];           // d_ac, then M00, S and its L D L^T
     __shared__ double sX[kMaxBlock * XS];                        // locations, centred on the block mean
     __shared__ __align__(16) double sW[kScr];                    // row buffers / partials / V stage
