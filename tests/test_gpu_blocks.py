@@ -123,3 +123,29 @@ def test_block_options_are_validated(cr, torch_dev):
         with pytest.raises(cr.CRError) as e:
             cr.fit(x, y, 0.05, 1e-4, opt)
         assert e.value.code == cr.CR_EINVAL
+
+
+def test_block_fit_paths_agree_bitwise(cr, torch_dev):
+    """The same kernels in the same order: host or device arrays, a served fit (the slot's arena)
+    and the allocation-free fit (the library's scratch) return identical results in K-block mode."""
+    torch = torch_dev
+    x, y = _data(60, 3, 21)
+    opt = _opt(cr, 12, check_every=25, max_iters=200)
+    print("block fit paths", flush=True)
+    ref = cr.fit(x, y, 0.05, 1e-6, opt, return_lambda=True)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    dev = cr.fit(xd, yd, 0.05, 1e-6, opt, return_lambda=True)
+    noal = cr.fit(xd, yd, 0.05, 1e-6, opt, return_lambda=True, no_alloc=True)
+    torch.cuda.synchronize()
+    with cr.Server(max_slots=2) as srv:
+        rid = srv.submit(x, y, 0.05, 1e-6, _opt(cr, 12, check_every=25, max_iters=200, keep_lambda=True))
+        served = srv.wait(rid)
+    for other in (dev, noal):
+        np.testing.assert_array_equal(other.y.cpu().numpy(), ref.y)
+        np.testing.assert_array_equal(other.xi.cpu().numpy(), ref.xi)
+        np.testing.assert_array_equal(other.lam.cpu().numpy(), ref.lam)
+        assert other.report["iters"] == ref.report["iters"]
+    np.testing.assert_array_equal(served.y, ref.y)
+    np.testing.assert_array_equal(served.xi, ref.xi)
+    np.testing.assert_array_equal(served.lam, ref.lam)
+    assert served.report["iters"] == ref.report["iters"]
