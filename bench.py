@@ -178,7 +178,7 @@ def cpu_baseline(x, ybar, delta: float, L: float, iters: int, rule: str, restart
 
 
 def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restart: bool,
-                rows_path: str | None = None, group_max_n: int = 0) -> dict:
+                rows_path: str | None = None, group_max_n: int = 0, rate: float = 50.0) -> dict:
     """Replay a Poisson stream of fit requests through the continuous-batching context.
 
     Requests (N log-uniform in [100, 6000], n uniform in 2..32, ||x||^2 or 8-piece log-sum-exp,
@@ -187,7 +187,7 @@ def run_serving(cr, W, count: int, slots: int, precision: str, rule: str, restar
     and queue wait the rest.  Per-request rows go to ``rows_path`` (JSON), never to stdout.
     """
     import numpy as np
-    reqs = W.serving_requests(count=count, seed=0)
+    reqs = W.serving_requests(count=count, rate_per_s=rate, seed=0)
     opt = cr.Options(precision=precision, step_rule=rule, restart=restart)
     ids = []
     with cr.Server(max_slots=slots, group_max_n=group_max_n) as srv:
@@ -472,6 +472,8 @@ def main() -> int:
                     help="also replay K requests of the serving stream (Poisson, 50/s) and report p50/p99 "
                          "latency and fits/s (0: skip)")
     ap.add_argument("--slots", type=int, default=8, help="resident fits of the serving context")
+    ap.add_argument("--serving-rate", type=float, default=50.0, metavar="R",
+                    help="mean arrival rate of the serving stream (requests/s)")
     ap.add_argument("--group-max-n", type=int, default=0,
                     help="serving: grouped iterations for fits with N <= this (0: per-slot launches)")
     ap.add_argument("--continuation", type=int, default=6, metavar="T",
@@ -702,7 +704,7 @@ def main() -> int:
     }
     if args.serving > 0:
         out["serving"] = run_serving(cr, W, args.serving, args.slots, args.precision, rule, restart,
-                                     args.serving_rows, args.group_max_n)
+                                     args.serving_rows, args.group_max_n, args.serving_rate)
     if args.continuation > 0:
         out["continuation"] = run_continuation(cr, W, args.continuation, args.precision)
     if not args.no_configs:
