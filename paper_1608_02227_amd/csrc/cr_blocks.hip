@@ -675,20 +675,25 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
             // dy = S^-1 r0 with L D L^T, in one wave: entries c = ln, ln + 64 in registers
             if (wid == 0) {
                 double v0 = ln < q ? sDy[ln] : 0.0, v1 = ln + 64 < q ? sDy[ln + 64] : 0.0;
+                // the loads are unconditional (rows clamped into the block) so that the unrolled
+                // steps can issue them ahead of the dependent updates
+                const int r0 = min(ln, q - 1), r1 = min(ln + 64, q - 1);
 #pragma unroll 4
                 for (int k = 0; k < q; ++k) {
-                    const double zk = (k < 64 ? read_lane(v0, k) : read_lane(v1, k - 64)) * sDi[k];
-                    if (ln > k && ln < q) v0 -= sS[ln * ld + k] * zk;
-                    if (ln + 64 > k && ln + 64 < q) v1 -= sS[(ln + 64) * ld + k] * zk;
+                    const double s0 = sS[r0 * ld + k], s1 = sS[r1 * ld + k], dik = sDi[k];
+                    const double zk = (k < 64 ? read_lane(v0, k) : read_lane(v1, k - 64)) * dik;
+                    if (ln > k && ln < q) v0 -= s0 * zk;
+                    if (ln + 64 > k && ln + 64 < q) v1 -= s1 * zk;
                 }
                 const double id0 = ln < q ? sDi[ln] : 0.0, id1 = ln + 64 < q ? sDi[ln + 64] : 0.0;
                 v0 *= id0;
                 v1 *= id1;
 #pragma unroll 4
                 for (int k = q - 1; k > 0; --k) {
+                    const double s0 = sS[k * ld + r0], s1 = sS[k * ld + r1];
                     const double xk = k < 64 ? read_lane(v0, k) : read_lane(v1, k - 64);
-                    if (ln < k) v0 -= sS[k * ld + ln] * id0 * xk;
-                    if (ln + 64 < k) v1 -= sS[k * ld + ln + 64] * id1 * xk;
+                    if (ln < k) v0 -= s0 * id0 * xk;
+                    if (ln + 64 < k) v1 -= s1 * id1 * xk;
                 }
                 if (ln < q) sDy[ln] = v0;
                 if (ln + 64 < q) sDy[ln + 64] = v1;
