@@ -127,3 +127,39 @@ def test_partial_dual_dominates_the_full_dual_and_is_below_the_optimum():
         # and the maximizing mu is the blocks' own multipliers: g(theta + mu) = g_K(theta)
         _, _, mu = B.eta(x, y, g, th, p)
         assert P.dual_objective(x, y, g, th + mu) == pytest.approx(gk, rel=1e-9, abs=1e-12)
+
+
+def test_block_arrowhead_elimination_needs_the_schur_complement():
+    """Reading of Theorem `lem:cholesky-block-arrowhead`: with M = G + A^T diag(d) A for one block
+    (G = diag(I, g I), A the block's pair rows), eliminating the xi blocks (z_a = M_aa^-1 b_a) leaves
+    the y system with S = M00 - sum_a M0a M_aa^-1 M0a^T; that elimination reproduces a dense solve,
+    while the same formula with M00 in place of S does not."""
+    rng = np.random.default_rng(12)
+    q, n, g = 6, 3, 0.05
+    xb = rng.uniform(-1, 1, size=(q, n))
+    A1, A2, _ = exact.explicit_constraints(xb)
+    A = np.hstack([A1, A2])
+    d = rng.exponential(1.0, size=A.shape[0]) * 10.0 ** rng.uniform(-3, 3, size=A.shape[0])
+    G = np.diag(np.concatenate([np.ones(q), g * np.ones(q * n)]))
+    M = G + A.T @ (d[:, None] * A)
+    b = rng.standard_normal(q + q * n)
+    ref = np.linalg.solve(M, b)
+    M00 = M[:q, :q]
+    blocks = [(M[:q, q + a * n:q + (a + 1) * n], M[q + a * n:q + (a + 1) * n, q + a * n:q + (a + 1) * n])
+              for a in range(q)]
+    # the xi blocks are block-diagonal: only point a's own n x n block couples xi_a
+    for a in range(q):
+        for c in range(q):
+            if c != a:
+                assert np.all(M[q + a * n:q + (a + 1) * n, q + c * n:q + (c + 1) * n] == 0.0)
+
+    def eliminate(Y):
+        r0 = b[:q] - sum(M0a @ np.linalg.solve(Maa, b[q + a * n:q + (a + 1) * n])
+                         for a, (M0a, Maa) in enumerate(blocks))
+        dy = np.linalg.solve(Y, r0)
+        dxi = [np.linalg.solve(Maa, b[q + a * n:q + (a + 1) * n] - M0a.T @ dy) for a, (M0a, Maa) in enumerate(blocks)]
+        return np.concatenate([dy, *dxi])
+
+    S = M00 - sum(M0a @ np.linalg.solve(Maa, M0a.T) for M0a, Maa in blocks)
+    np.testing.assert_allclose(eliminate(S), ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+    assert np.abs(eliminate(M00) - ref).max() > 1e-3 * np.abs(ref).max()
