@@ -109,7 +109,9 @@ typedef struct {
                                 contiguous blocks of p points (the last may be shorter; at least two
                                 blocks), only the pairs between blocks dualized, and Step 1 solving
                                 each block's QP (eq. "eq:step1-problem") by a primal-dual interior-
-                                point method on the device.  Needs CR_FP64 and the constant step
+                                point method on the device (each Step 1 after a solver's first starts
+                                from the slacks and multipliers the previous one ended on, lifted
+                                into the interior).  Needs CR_FP64 and the constant step
                                 (step_rule 0).  The returned multipliers are then theta (between
                                 blocks) plus the blocks' own multipliers (inside the blocks). */
     int32_t reserved2;
