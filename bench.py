@@ -345,7 +345,25 @@ def block_ipm_flops(q: int, n: int) -> int:
             + 2 * (4 * q * n * n + 4 * q * q) + 6 * 2 * pairs * n)
 
 
-def run_kblock(cr, W, torch, iters: int, converge_tol: float = 0.0) -> dict:
+def kblock_cpu_baseline(W, p: int, n: int, N: int, delta: float) -> dict:
+    """The block oracle, untuned, on the host: the exact projection (NNLS on the dual) of the first
+    block's Step-1 QP at the first iteration (theta = 0, so eta0 = (ybar, 0)) of the K-block leg's
+    workload; one block of the N / p a Step 1 solves."""
+    import importlib
+    import numpy as np
+    ob = importlib.import_module("oracle.blocks")
+    x, yb = W.paper_shaped(N, n, "quadratic", 0)
+    host = host_description()
+    t0 = time.perf_counter()
+    ob.project_block(x[:p], yb[:p], np.zeros((p, n)), delta)
+    dt = time.perf_counter() - t0
+    log(f"k-block cpu baseline: one block projection {dt:.1f} s")
+    return {"value": round(dt, 2), "unit": "s per block projection", "cores": host["blas_threads"] or os.cpu_count(),
+            "kind": "oracle", "sample": f"block 0 of {-(-N // p)} at the first Step 1 (exact, NNLS)",
+            "step1_s_estimate": round(dt * -(-N // p), 1)}
+
+
+def run_kblock(cr, W, torch, iters: int, converge_tol: float = 0.0, cpu: bool = False) -> dict:
     """K-block partial dualization (Section 2.1) at the paper's block setting of Section 4 (blocks of
     100 points, n = 20; N = 2400 is its largest, K = 24), on the paper-shaped quadratic generator:
     FP64 constant-step P-APG, `iters` iterations timed after one warm-up, with the blocks and with
@@ -397,6 +415,8 @@ def run_kblock(cr, W, torch, iters: int, converge_tol: float = 0.0) -> dict:
                          "kkt": _g4(r.report["kkt"])}
             log(f"k-block convergence N={Nc}: {key} {r.report['iters']} iterations in {conv[key]['s']} s")
         out["converge"] = conv
+    if cpu:
+        out["cpu_baseline"] = kblock_cpu_baseline(W, p, n, N, delta)
     return out
 
 
@@ -488,6 +508,8 @@ def main() -> int:
                     help="run only the K-block leg and print it as one JSON line")
     ap.add_argument("--kblock-converge", type=float, default=0.0, metavar="TOL",
                     help="with --kblock-only: also fit both partitions to this KKT tolerance at N=800")
+    ap.add_argument("--kblock-cpu", action="store_true",
+                    help="with --kblock-only: time the block oracle's exact projection of one block")
     ap.add_argument("--probe", type=int, default=0, metavar="N",
                     help="only run the memory probes at the pass geometry of an N-point, n=40 fit and print "
                          "their JSON line (no fits)")
@@ -514,8 +536,8 @@ def main() -> int:
         print(json.dumps({"probe": run_probe(torch, cr, args.probe, 40, 20)}), flush=True)
         return 0
     if args.kblock_only:
-        print(json.dumps({"kblock": run_kblock(cr, W, torch, max(args.kblock, 1), args.kblock_converge)},
-                         separators=(",", ":")), flush=True)
+        print(json.dumps({"kblock": run_kblock(cr, W, torch, max(args.kblock, 1), args.kblock_converge,
+                                               args.kblock_cpu)}, separators=(",", ":")), flush=True)
         return 0
     dev = torch.device("cuda:0")
     wl = W.WORKLOADS[WORKLOAD]
