@@ -113,7 +113,8 @@ typedef struct {
                                 from the slacks and multipliers the previous one ended on, lifted
                                 into the interior).  Needs CR_FP64 and the constant step
                                 (step_rule 0).  The returned multipliers are then theta (between
-                                blocks) plus the blocks' own multipliers (inside the blocks). */
+                                blocks) plus the blocks' own multipliers (inside the blocks); a warm
+                                start's entries inside the blocks are ignored. */
     int32_t reserved2;
     const double *lambda0;   /* optional N x N warm start lam^0 (its diagonal is ignored; entries
                                 must be finite and >= 0, else CR_EINVAL), in the memory of the call's

@@ -475,6 +475,12 @@ int cr_solver_create_impl(int64_t N, int64_t n, const double *x, const double *y
         if (on_device) H(hipMemcpy(hl.data(), lambda0, hl.size() * 8, hipMemcpyDeviceToHost));
         else std::memcpy(hl.data(), lambda0, hl.size() * 8);
         for (int64_t i = 0; i < N; ++i) hl[(size_t)i * N + i] = 0.0;
+        // K-block partial dualization: only the pairs between blocks carry multipliers; the
+        // entries inside a block are not variables (Step 1 recomputes the blocks' own)
+        if (s->blk > 1)
+            for (int64_t i = 0; i < N; ++i)
+                for (int64_t j = 0; j < N; ++j)
+                    if (i / s->blk == j / s->blk) hl[(size_t)i * N + j] = 0.0;
         for (double v : hl)
             if (!std::isfinite(v) || v < 0.0) { H(hipStreamSynchronize(s->stream)); return bail(CR_EINVAL); }
         H(hipMemcpyAsync(dl, hl.data(), hl.size() * 8, hipMemcpyHostToDevice, s->stream));

@@ -149,3 +149,21 @@ def test_block_fit_paths_agree_bitwise(cr, torch_dev):
     np.testing.assert_array_equal(served.xi, ref.xi)
     np.testing.assert_array_equal(served.lam, ref.lam)
     assert served.report["iters"] == ref.report["iters"]
+
+
+def test_block_warm_start_ignores_the_entries_inside_blocks(cr, torch_dev):
+    """A K-block fit returns theta plus the blocks' own multipliers; as a warm start only theta (the
+    pairs between blocks) is a variable, so the returned array and its inter-block part start the
+    same fit."""
+    N, n, p = 48, 2, 12
+    x, y = _data(N, n, 31)
+    opt = _opt(cr, p, check_every=25)
+    prev = cr.fit(x, y + 0.01, 0.05, 1e-3, opt, return_lambda=True)
+    inter = B.inter_mask(N, p)
+    assert np.any(prev.lam[~inter] > 0.0)
+    print("block warm start", flush=True)
+    a = cr.fit(x, y, 0.05, 1e-5, opt, return_lambda=True, lambda0=prev.lam)
+    b = cr.fit(x, y, 0.05, 1e-5, opt, return_lambda=True, lambda0=prev.lam * inter)
+    np.testing.assert_array_equal(a.y, b.y)
+    np.testing.assert_array_equal(a.lam, b.lam)
+    assert a.report["iters"] == b.report["iters"]
