@@ -167,3 +167,22 @@ def test_block_warm_start_ignores_the_entries_inside_blocks(cr, torch_dev):
     np.testing.assert_array_equal(a.y, b.y)
     np.testing.assert_array_equal(a.lam, b.lam)
     assert a.report["iters"] == b.report["iters"]
+
+
+def test_block_continuation_is_certified(cr, torch_dev):
+    """The continuation (Section 2.4.1) with a K-block partition: every outer step ends at a
+    certified gap <= delta_t, and the last iterate lies within sqrt(2 G) + sqrt(2 G') of the
+    singleton partition's (both within sqrt(2 G) of the same regularized minimizer, Theorem
+    `thm:rate`)."""
+    x, y = _data(40, 2, 3)
+    runs = {}
+    for p in (0, 10):
+        opt = cr.Options(precision="fp64", step_rule="constant", block_size=p, max_iters=400000)
+        print(f"block continuation p={p}", flush=True)
+        r = cr.fit_continuation(x, y, 1.0, 2.0, 1e-2, 1.0, 3, opt)
+        assert r.status == cr.CR_OK
+        for st in r.extra["steps"]:
+            assert st["cert_gap"] <= st["delta"]
+        runs[p] = (r.y, r.extra["steps"][-1]["cert_gap"])
+    (ya, ga), (yb, gb) = runs[0], runs[10]
+    assert np.linalg.norm(ya - yb) <= np.sqrt(2 * ga) + np.sqrt(2 * gb)
