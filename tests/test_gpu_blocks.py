@@ -186,3 +186,29 @@ def test_block_continuation_is_certified(cr, torch_dev):
         runs[p] = (r.y, r.extra["steps"][-1]["cert_gap"])
     (ya, ga), (yb, gb) = runs[0], runs[10]
     assert np.linalg.norm(ya - yb) <= np.sqrt(2 * ga) + np.sqrt(2 * gb)
+
+
+def test_block_iterates_at_the_papers_block_size_match_the_stored_oracle_run(cr, torch_dev):
+    """Blocks of 100 points (the paper's size; N = 150: a full block and a ragged one of 50), against
+    the oracle's exact-projection run stored by tests/golden/make_block_golden.py: every element of
+    theta^k at k = 1, 2, 3, 5 within 1e-6 of the multiplier scale, the entries inside the blocks 0."""
+    import json
+    import os
+    from paper_1608_02227_amd import workloads as W
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "blocks_N150_n2_p100_seed7.npz")
+    d = np.load(path, allow_pickle=False)
+    meta = json.loads(str(d["meta"]))
+    N, n, p, g = meta["N"], meta["n"], meta["p"], meta["gamma"]
+    x, y = W.sq_norm(N, n, meta["noise"], meta["seed"])
+    print(f"block iterates at p={p}", flush=True)
+    with cr.Solver(x, y, g, _opt(cr, p)) as s:
+        s.set_L(meta["L"])
+        done = 0
+        for k in meta["ks"]:
+            s.iterate(k - done)
+            done = k
+            got, ref = s.lam(), d[f"theta_{k}"]
+            err = np.max(np.abs(got - ref)) / max(np.abs(ref).max(), 1e-300)
+            print(f"  k={k}: {err:.2e}", flush=True)
+            assert err <= 1e-6, k
+            assert np.all(got[~B.inter_mask(N, p)] == 0.0)
