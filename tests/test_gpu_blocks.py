@@ -188,14 +188,16 @@ def test_block_continuation_is_certified(cr, torch_dev):
     assert np.linalg.norm(ya - yb) <= np.sqrt(2 * ga) + np.sqrt(2 * gb)
 
 
-def test_block_iterates_at_the_papers_block_size_match_the_stored_oracle_run(cr, torch_dev):
-    """Blocks of 100 points (the paper's size; N = 150: a full block and a ragged one of 50), against
-    the oracle's exact-projection run stored by tests/golden/make_block_golden.py: every element of
-    theta^k at k = 1, 2, 3, 5 within 1e-6 of the multiplier scale, the entries inside the blocks 0."""
+@pytest.mark.parametrize("name", ["blocks_N150_n2_p100_seed7", "blocks_N120_n20_p100_seed8"])
+def test_block_iterates_at_the_papers_block_size_match_the_stored_oracle_run(cr, torch_dev, name):
+    """Blocks of 100 points (the paper's size: a full block and a ragged one; n = 2 and the paper's
+    n = 20), against the oracle's exact-projection run stored by tests/golden/make_block_golden.py:
+    every element of the stored theta^k within 1e-6 of the multiplier scale, the entries inside the
+    blocks 0."""
     import json
     import os
     from paper_1608_02227_amd import workloads as W
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "blocks_N150_n2_p100_seed7.npz")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".npz")
     d = np.load(path, allow_pickle=False)
     meta = json.loads(str(d["meta"]))
     N, n, p, g = meta["N"], meta["n"], meta["p"], meta["gamma"]
