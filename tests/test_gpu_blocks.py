@@ -125,20 +125,23 @@ def test_block_options_are_validated(cr, torch_dev):
         assert e.value.code == cr.CR_EINVAL
 
 
-def test_block_fit_paths_agree_bitwise(cr, torch_dev):
+# a small block (n <= 16 bucket) and the paper's block size with its n = 20 (n <= 32 bucket, a
+# ragged last block)
+@pytest.mark.parametrize("N,n,p,iters", [(60, 3, 12, 200), (130, 20, 100, 60)])
+def test_block_fit_paths_agree_bitwise(cr, torch_dev, N, n, p, iters):
     """The same kernels in the same order: host or device arrays, a served fit (the slot's arena)
     and the allocation-free fit (the library's scratch) return identical results in K-block mode."""
     torch = torch_dev
-    x, y = _data(60, 3, 21)
-    opt = _opt(cr, 12, check_every=25, max_iters=200)
-    print("block fit paths", flush=True)
+    x, y = _data(N, n, 21)
+    opt = _opt(cr, p, check_every=25, max_iters=iters)
+    print(f"block fit paths N={N} n={n} p={p}", flush=True)
     ref = cr.fit(x, y, 0.05, 1e-6, opt, return_lambda=True)
     xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
     dev = cr.fit(xd, yd, 0.05, 1e-6, opt, return_lambda=True)
     noal = cr.fit(xd, yd, 0.05, 1e-6, opt, return_lambda=True, no_alloc=True)
     torch.cuda.synchronize()
     with cr.Server(max_slots=2) as srv:
-        rid = srv.submit(x, y, 0.05, 1e-6, _opt(cr, 12, check_every=25, max_iters=200, keep_lambda=True))
+        rid = srv.submit(x, y, 0.05, 1e-6, _opt(cr, p, check_every=25, max_iters=iters, keep_lambda=True))
         served = srv.wait(rid)
     for other in (dev, noal):
         np.testing.assert_array_equal(other.y.cpu().numpy(), ref.y)
