@@ -836,10 +836,19 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
 hipError_t launch_block_project(const Geometry &g, const BlockProjArgs &a, hipStream_t st) {
     if (a.p < 1 || a.p > kMaxBlock || a.n < 1 || a.n > 16 * kMaxMB) return hipErrorInvalidValue;
     const int blocks = (g.N + a.p - 1) / a.p;
+    // the smallest compile-time bound NB >= n: the per-point vectors are NB doubles in registers
     if (a.n <= 16)
         hipLaunchKernelGGL(block_ipm_kernel<16>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 24)
+        hipLaunchKernelGGL(block_ipm_kernel<24>, dim3(blocks), dim3(kBT), 0, st, a);
     else if (a.n <= 32)
         hipLaunchKernelGGL(block_ipm_kernel<32>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 40)
+        hipLaunchKernelGGL(block_ipm_kernel<40>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 48)
+        hipLaunchKernelGGL(block_ipm_kernel<48>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 56)
+        hipLaunchKernelGGL(block_ipm_kernel<56>, dim3(blocks), dim3(kBT), 0, st, a);
     else
         hipLaunchKernelGGL(block_ipm_kernel<64>, dim3(blocks), dim3(kBT), 0, st, a);
     return hipGetLastError();
