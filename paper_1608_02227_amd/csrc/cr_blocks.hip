@@ -837,8 +837,14 @@ hipError_t launch_block_project(const Geometry &g, const BlockProjArgs &a, hipSt
     if (a.p < 1 || a.p > kMaxBlock || a.n < 1 || a.n > 16 * kMaxMB) return hipErrorInvalidValue;
     const int blocks = (g.N + a.p - 1) / a.p;
     // the smallest compile-time bound NB >= n: the per-point vectors are NB doubles in registers
-    if (a.n <= 16)
+    if (a.n <= 8)
+        hipLaunchKernelGGL(block_ipm_kernel<8>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 12)
+        hipLaunchKernelGGL(block_ipm_kernel<12>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 16)
         hipLaunchKernelGGL(block_ipm_kernel<16>, dim3(blocks), dim3(kBT), 0, st, a);
+    else if (a.n <= 20)
+        hipLaunchKernelGGL(block_ipm_kernel<20>, dim3(blocks), dim3(kBT), 0, st, a);
     else if (a.n <= 24)
         hipLaunchKernelGGL(block_ipm_kernel<24>, dim3(blocks), dim3(kBT), 0, st, a);
     else if (a.n <= 32)

@@ -38,10 +38,11 @@ def _opt(cr, p, **kw):
     return cr.Options(precision="fp64", step_rule="constant", block_size=p, **kw)
 
 
-# every feature bucket of the kernel (n <= 16, 24, 32, 40, 48, 56, 64; n = 63 the largest), the factor
+# every feature bucket of the kernel (n <= 8, 12, 16, 20, 24, 32, 40, 48, 56, 64; n = 63 the largest), the factor
 # in LDS or not (n <= 27), a ragged last block and a last block of one point, n = 1
 @pytest.mark.parametrize("N,n,p", [(48, 2, 12), (45, 3, 10), (40, 5, 8), (36, 20, 12), (32, 30, 8), (30, 40, 10),
-                                   (24, 44, 8), (22, 52, 10), (20, 63, 10), (41, 2, 10), (30, 1, 8)])
+                                   (24, 44, 8), (22, 52, 10), (20, 63, 10), (30, 10, 10), (24, 22, 8),
+                                   (41, 2, 10), (30, 1, 8)])
 def test_block_iterates_match_oracle(cr, torch_dev, N, n, p):
     x, y = _data(N, n, N + n)
     g = 0.05
