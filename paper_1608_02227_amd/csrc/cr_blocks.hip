@@ -608,7 +608,7 @@ __global__ __launch_bounds__(kBT) void block_ipm_kernel(BlockProjArgs A) {
 
         // Newton system M d_eta = -r_d + A^T wv with wv = d (-r_p) + r_c / s; r_c the
         // complementarity right-hand side (predictor: -s theta; corrector adds -ds_aff dth_aff + sig mu)
-        auto solve = [&](bool corrector, double sigmu) {
+        auto solve = [&](bool corrector, double sigmu) __attribute__((always_inline)) {
             // right-hand side: y part -r_d + (column sum - row sum) of wv, xi part
             // -r_d + sum_c wv_ac (x_a - x_c)
             double c0 = 0.0, c1 = 0.0;
